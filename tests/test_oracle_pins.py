@@ -1,0 +1,255 @@
+"""Pins of the FP64 oracle against facts fixed outside it (CPU only).
+
+Each test checks the oracle against something it cannot simply restate:
+a brute-force sum, a closed form, an identity, a library special case or a
+Gaussian expectation.  The comment on each test names the plausible mistake
+it would catch.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.signal
+import scipy.special
+
+import oracle
+from synthetic import bandlimited_noise, seeded_rng, unit_hann_chirp, get_workload, make_segment
+
+
+def _rng(seed):
+    return np.random.default_rng(seed)
+
+
+def _brute_force(y, w):
+    """Pure-Python circular correlation: rho[n] = sum_m w[m] y[(n+m) % N]."""
+    n = len(y)
+    out = []
+    for lag in range(n):
+        acc = 0.0
+        for m in range(len(w)):
+            acc += w[m] * y[(lag + m) % n]
+        out.append(acc)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("n,l", [(8, 1), (8, 3), (8, 8), (16, 4), (16, 16), (64, 1), (64, 16), (64, 64),
+                                 (256, 3), (256, 64), (1024, 1), (1024, 3), (1024, 256)])
+def test_fft_and_direct_match_brute_force(n, l):
+    # catches: conj on the wrong operand, a wrong irfft normalisation, a shifted or reversed lag
+    r = _rng(1000 * n + l)
+    y = r.standard_normal(n)
+    w = r.standard_normal(l)
+    ref = _brute_force(list(y), list(w))
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(oracle.correlate_fft(y, w) - ref)) <= 1e-12 * scale
+    assert np.max(np.abs(oracle.correlate_direct(y, w) - ref)) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("n0", [0, 5, 1023])
+def test_impulse_closed_form(n0):
+    # y = delta at n0  =>  rho[n] = w[(n0 - n) mod N]; catches a lag sign error
+    n, l = 1024, 100
+    w = _rng(7).standard_normal(l)
+    y = np.zeros(n)
+    y[n0] = 1.0
+    wpad = np.zeros(n)
+    wpad[:l] = w
+    expect = wpad[(n0 - np.arange(n)) % n]
+    np.testing.assert_allclose(oracle.correlate_fft(y, w), expect, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("q,l,phi", [(3, 100, 0.0), (37, 1000, 0.7), (200, 4096, -1.1)])
+def test_rectangular_template_tone_closed_form(q, l, phi):
+    # w = 1 on L samples, y = cos(2 pi q n / N + phi): Dirichlet-kernel closed form
+    n = 8192
+    y = np.cos(2 * np.pi * q * np.arange(n) / n + phi)
+    w = np.ones(l)
+    k = np.arange(n)
+    amp = math.sin(math.pi * q * l / n) / math.sin(math.pi * q / n)
+    expect = amp * np.cos(2 * np.pi * q * k / n + phi + math.pi * q * (l - 1) / n)
+    np.testing.assert_allclose(oracle.correlate_fft(y, w), expect, rtol=0, atol=1e-9 * abs(amp) + 1e-10)
+
+
+def test_parseval_identity_any_input():
+    # Eq. (6) time domain == its exact Parseval form for any real input, including DC and Nyquist power
+    r = _rng(3)
+    n = 4096
+    for trial in range(5):
+        y = r.standard_normal(n) + (0.3 if trial % 2 else 0.0)
+        w = r.standard_normal(300)
+        rho = oracle.correlate_fft(y, w)
+        c = np.fft.rfft(rho)
+        st = oracle.sigma_time(rho)
+        sf = oracle.sigma_parseval(c, n)
+        assert abs(st - sf) <= 1e-12 * st
+        # the naive time-domain RMS, written out
+        assert abs(st - math.sqrt(sum(v * v for v in rho) / n)) <= 1e-12 * st
+
+
+def test_eq7_equals_parseval_for_bandlimited_only():
+    # the paper's sqrt(2)/N form omits C_0 and C_{N/2}: exact for band-limited data, biased otherwise
+    n, fs = 8192, 4096.0
+    y = bandlimited_noise(n, fs, seeded_rng(99, 0, 0, "noise"))
+    w = oracle.chirp_template(800.0, 100.0, 1024, fs)
+    rho = oracle.correlate_fft(y, w)
+    c = np.fft.rfft(rho)
+    assert abs(oracle.sigma_eq7(c, n) - oracle.sigma_parseval(c, n)) <= 1e-12 * oracle.sigma_parseval(c, n)
+    y2 = y + 0.5  # DC offset: C_0 != 0
+    rho2 = oracle.correlate_fft(y2, np.ones(64))
+    c2 = np.fft.rfft(rho2)
+    assert oracle.sigma_eq7(c2, n) < 0.9 * oracle.sigma_parseval(c2, n)
+    assert abs(oracle.sigma_parseval(c2, n) - oracle.sigma_time(rho2)) <= 1e-12 * oracle.sigma_time(rho2)
+
+
+def test_sigma_expectation_equals_inband_template_energy():
+    # E[sigma^2] over band-limited unit noise = (1/N) sum_{k in band} |W_k|^2 (full spectrum);
+    # catches a wrong 1/N or a factor 2 in sigma.  Template straddles the 350 Hz edge.
+    n, fs = 4096, 4096.0
+    w = oracle.chirp_template(250.0, 800.0, 1024, fs)  # 250 -> 450 Hz over 0.25 s
+    wk = np.fft.fft(np.concatenate([w, np.zeros(n - len(w))]))
+    f = np.abs(np.fft.fftfreq(n, d=1.0 / fs))
+    band = (f >= 350.0) & (f <= 2000.0) & (f > 0) & (f < fs / 2)
+    expect = np.sum(np.abs(wk[band]) ** 2) / n
+    assert 0.2 < expect < 0.9
+    vals = []
+    for s in range(400):
+        y = bandlimited_noise(n, fs, seeded_rng(77, 0, s, "noise"))
+        vals.append(oracle.sigma_time(oracle.correlate_fft(y, w)) ** 2)
+    vals = np.array(vals)
+    sem = vals.std(ddof=1) / math.sqrt(len(vals))
+    assert abs(vals.mean() - expect) < 5 * sem + 1e-3 * expect
+
+
+def test_gaussian_exceedance_fractions():
+    # pooled P(|rho|/sigma > kappa) ~ erfc(kappa/sqrt 2) for band-limited Gaussian noise (Sec. 3).
+    # Wide-band chirps keep the effective sample count high; dividing by the realised sigma of each
+    # correlation still trims the far tail slightly, hence the looser bound at kappa = 3.
+    n, fs = 8192, 4096.0
+    templates = [oracle.chirp_template(f0, fd, 1024, fs) for f0 in (500.0, 900.0, 1300.0, 1700.0)
+                 for fd in (-1600.0, 0.0, 1600.0)]
+    counts = {1.0: 0, 2.0: 0, 3.0: 0}
+    total = 0
+    for s in range(64):
+        y = bandlimited_noise(n, fs, seeded_rng(55, 0, s, "noise"))
+        rho = oracle.correlate_fft(y, np.array(templates))
+        z = np.abs(rho) / oracle.sigma_time(rho)[:, None]
+        for k in counts:
+            counts[k] += int(np.sum(z > k))
+        total += z.size
+    for k, c in counts.items():
+        p = scipy.special.erfc(k / math.sqrt(2.0))
+        tol = 0.05 if k < 3 else 0.20
+        assert abs(c / total - p) <= tol * p, (k, c / total, p)
+
+
+def test_hann_is_numpy_symmetric_hann():
+    for l in (2, 3, 16, 1024, 4097):
+        np.testing.assert_allclose(oracle.hann(l), np.hanning(l), rtol=0, atol=1e-15)
+    assert oracle.hann(1).tolist() == [1.0]
+
+
+def test_chirp_quarter_rate_tone_exact():
+    # f0 = fs/4, fdot = 0, untapered: cos(pi m / 2) = 1, 0, -1, 0, ...
+    w = oracle.chirp_template(1024.0, 0.0, 16, 4096.0, taper=False, normalize=False)
+    np.testing.assert_allclose(w, np.tile([1.0, 0.0, -1.0, 0.0], 4), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("f0,fdot", [(600.0, 300.0), (1500.0, -400.0)])
+def test_chirp_instantaneous_frequency(f0, fdot):
+    # local frequency of the untapered chirp is f0 + fdot t (pins the 1/2 in the phase and fdot's sign)
+    fs, l = 4096.0, 4096
+    w = oracle.chirp_template(f0, fdot, l, fs, taper=False, normalize=False)
+    ph = np.unwrap(np.angle(scipy.signal.hilbert(w)))
+    finst = np.diff(ph) * fs / (2 * np.pi)
+    t = (np.arange(l - 1) + 0.5) / fs
+    mid = slice(200, l - 200)
+    assert np.max(np.abs(finst[mid] - (f0 + fdot * t[mid]))) < 2.0
+
+
+def test_template_unit_energy_and_grid_order():
+    f0, fd, tau = oracle.grid_params(3, 4, (400.0, 800.0), (-100.0, 200.0), (0.5, 1.0))
+    assert f0.tolist() == [400.0] * 4 + [600.0] * 4 + [800.0] * 4
+    assert fd.tolist() == [-100.0, 0.0, 100.0, 200.0] * 3
+    assert tau.tolist() == [0.5, 1.0] * 6
+    for w in oracle.template_bank(f0, fd, tau, 4096.0):
+        assert abs(np.dot(w, w) - 1.0) < 1e-13
+
+
+def test_cauchy_schwarz_recovers_noise_free_injection():
+    # y = A * (unit chirp of grid point j) at lag n0, no noise: the raw |rho| maximum over the
+    # bank is A exactly, at (j, n0); the injected chirp is built by the input generator's own code.
+    w = get_workload("C1")
+    f0, fd, tau = w.template_params()
+    bank = oracle.template_bank(f0, fd, tau, w.fs)
+    n, amp, j_true, n0 = w.n, 7.5, 19, 3001
+    y = np.zeros(n)
+    s = unit_hann_chirp(f0[j_true], fd[j_true], int(round(tau[j_true] * w.fs)), w.fs)
+    y[n0:n0 + len(s)] = amp * s
+    rho = oracle.correlate_fft(y, np.array(bank))
+    j, lag = np.unravel_index(np.argmax(np.abs(rho)), rho.shape)
+    assert (j, lag) == (j_true, n0)
+    assert abs(rho[j, lag] - amp) < 1e-12 * amp
+    others = np.abs(np.delete(rho, j_true, axis=0))
+    assert others.max() < amp * (1 - 1e-6)
+
+
+def test_threshold_strict_and_absolute():
+    sigma, kappa = 2.0, 3.0
+    rho = np.array([6.0, -6.0, 6.0000001, -6.0000001, 5.9, -7.0, 0.0])
+    assert oracle.threshold_tails(rho, sigma, kappa).tolist() == [2, 3, 5]
+    assert oracle.threshold_tails(rho, 0.0, kappa).tolist() == []
+
+
+def test_shift_equivariance_and_linearity():
+    r = _rng(11)
+    n = 2048
+    y1, y2 = r.standard_normal(n), r.standard_normal(n)
+    w = r.standard_normal(200)
+    rho1 = oracle.correlate_fft(y1, w)
+    np.testing.assert_allclose(oracle.correlate_fft(np.roll(y1, 37), w), np.roll(rho1, 37), atol=1e-11)
+    np.testing.assert_allclose(oracle.correlate_fft(2.0 * y1 - 3.0 * y2, w),
+                               2.0 * rho1 - 3.0 * oracle.correlate_fft(y2, w), atol=1e-11)
+
+
+def test_search_tails_equal_brute_force_threshold():
+    # the full search (batched FFT, sigma, strict threshold, sort) against brute force at tiny N
+    r = _rng(5)
+    segs = [r.standard_normal(64), r.standard_normal(64)]
+    temps = [r.standard_normal(5), r.standard_normal(16), r.standard_normal(1)]
+    kappa = 1.5
+    out = oracle.search(segs, temps, kappa, keep_rho=True)
+    expect = []
+    for s, y in enumerate(segs):
+        for j, w in enumerate(temps):
+            rho = _brute_force(list(y), list(w))
+            sig = math.sqrt(sum(v * v for v in rho) / len(rho))
+            assert abs(out["sigma"][s, j] - sig) <= 1e-12 * sig
+            assert abs(out["sigma_f"][s, j] - sig) <= 1e-12 * sig
+            for lag, v in enumerate(rho):
+                if abs(v) > kappa * sig:
+                    expect.append((s, j, lag, v))
+    got = out["tails"]
+    assert [(int(a), int(b), int(c)) for a, b, c, _ in got] == [(a, b, c) for a, b, c, _ in expect]
+    np.testing.assert_allclose(got["rho"], [e[3] for e in expect], rtol=1e-12, atol=1e-12)
+
+
+def test_c1_injection_recovered_by_raw_rho():
+    # C1: SNR-20 chirp (600 Hz, +50 Hz/s, 0.25 s) in band-limited noise; the raw-|rho| maximum
+    # sits at f0 = 600 Hz with fdot on one of the two neighbouring grid values, near the offset
+    w = get_workload("C1")
+    y, inj = make_segment(w, 0)
+    f0, fd, tau = w.template_params()
+    bank = oracle.template_bank(f0, fd, tau, w.fs)
+    out = oracle.search([y], bank, w.kappa, keep_rho=True)
+    rho = out["rho"][0]
+    noise_out = oracle.search([_noise_only(w)], bank, w.kappa)
+    assert len(out["tails"]) > 50
+    assert len(out["tails"]) > 2 * max(1, len(noise_out["tails"]))
+    j, lag = np.unravel_index(np.argmax(np.abs(rho)), rho.shape)
+    assert f0[j] == 600.0
+    assert np.min(np.abs(fd[j] - np.array([200.0 / 7, 600.0 / 7]))) < 1e-9
+    assert abs(int(lag) - inj[0].offset) <= 512
+
+
+def _noise_only(w):
+    return bandlimited_noise(w.n, w.fs, seeded_rng(w.config_id, 0, 0, "noise"))
