@@ -1,0 +1,200 @@
+"""Benchmark of the matched-filter hot path on one MI355X.
+
+A step is one pass of the hot path over one batch: the segment's forward real
+FFT, the fused kernel over every template of the resident bank (product,
+FP64 Parseval sigma, inverse FFT on chip, threshold, ballot compaction) and
+the fetch of the sorted tails to the host.  The template bank (chirp
+synthesis and forward FFT of every template) is built once per plan, as the
+paper loads precomputed template transforms (Sec. 3.2, step (ii)); its build
+time is reported beside the step rate.
+
+Prints one JSON line.  With no flags: N = 1 GPU, workload C2 (N = 2^16,
+8192 one-second chirps, kappa = 5, FP32), 20 timed steps after 3 warmups.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
+PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
+
+
+def nominal_flops(n: int) -> float:
+    """5 N log2 N per correlation: the paper's FFT cost convention (Eq. 10, Sec. 3.2)."""
+    return 5.0 * n * math.log2(n)
+
+
+def algorithmic_flops(n: int) -> float:
+    """Per correlation in the fused kernel: inverse real FFT (2.5 N log2 N), the complex
+    product over N/2+1 bins (6 each) and the threshold (1 per lag)."""
+    return 2.5 * n * math.log2(n) + 6.0 * (n // 2 + 1) + n
+
+
+def algorithmic_bytes(n: int, spec_bytes: int) -> float:
+    """Per correlation: one template spectrum row read from HBM (N/2 packed complex values)."""
+    return (n // 2) * spec_bytes
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="C2")
+    p.add_argument("--precision", default="f32")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-fp16", action="store_true")
+    p.add_argument("--cpu-templates", type=int, default=2048,
+                   help="templates in the bounded oracle sample")
+    p.add_argument("--copy-calibration-mib", type=int, default=0,
+                   help="also run a plain torch copy of this size (HBM counter calibration)")
+    return p.parse_args()
+
+
+def run_plan(bfs, torch, w, y_dev, precision, steps, warmup):
+    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
+    t0 = time.perf_counter()
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        with plan.filter(y_dev) as job:
+            job.fetch_tails()
+    torch.cuda.synchronize()
+    corr_ms, lat_ms, n_tails = [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        job = plan.filter(y_dev)
+        tails, total = job.fetch_tails()
+        lat_ms.append((time.perf_counter() - ts) * 1e3)
+        corr_ms.append(job.timing()[0])
+        n_tails = total
+        job.release()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    info = {"bank_bytes": plan.bank_bytes, "threads": plan.threads_per_correlation}
+    plan.close()
+    return wall, build_s, corr_ms, lat_ms, n_tails, info
+
+
+def cpu_baseline(w, y, n_templates):
+    import oracle
+
+    f0, fd, tau = w.template_params()
+    ids = list(range(min(n_templates, w.n_templates)))
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    bank = oracle.template_bank(f0, fd, tau, w.fs, ids=ids)
+    oracle.search([y.astype("float64")], bank, w.kappa)
+    dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": len(ids) / dt, "unit": "correlations/s", "cores": cores, "kind": "oracle",
+            "sample": f"{w.name}: segment 0 against templates 0..{len(ids) - 1} (FP64 scipy.fft, "
+                      f"template synthesis included), {dt:.1f} s", "cpu": cpu}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(template- or segment-parallel sharding needs no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1708_01609_amd import build as b
+
+    if not os.path.exists(b.LIB):
+        b.build()
+    from paper_1708_01609_amd import bfsearch as bfs
+    from synthetic import get_workload, make_segment
+
+    w = get_workload(args.workload)
+    y, _ = make_segment(w, 0)
+    dt = torch.float64 if args.precision == "f64" else torch.float32
+    y_dev = torch.from_numpy(np.ascontiguousarray(y[None, :])).to(device="cuda:0", dtype=dt)
+
+    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, args.precision,
+                                                             args.steps, args.warmup)
+    k = w.n_templates
+    value = args.steps * k / wall
+    corr_avg_s = float(np.mean(corr_ms)) * 1e-3
+    spec_bytes = {"f64": 16, "f32": 8, "f32-w16f": 4, "f32-w16b": 4}[args.precision]
+    achieved = algorithmic_flops(w.n) * k / corr_avg_s
+    line = {
+        "metric": "correlations/s (N=2^16, tau=1 s) on 1 MI355X",
+        "value": value,
+        "unit": "correlations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.description}", "n": w.n, "templates": k, "segments": 1,
+                   "kappa": w.kappa, "precision": args.precision},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "corr_kernel (fused product, sigma, inverse FFT, threshold, compaction)",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_VECTOR,
+            "traffic": None,
+            "flops_per_correlation": algorithmic_flops(w.n),
+            "correlations_per_launch": k,
+            "kernel_ms_avg": corr_avg_s * 1e3,
+            "hbm_algorithmic_GBps": algorithmic_bytes(w.n, spec_bytes) * k / corr_avg_s / 1e9,
+        },
+        "kernel_rate": k / corr_avg_s,
+        "nominal_tflops": nominal_flops(w.n) * value / 1e12,
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "max": float(np.max(lat_ms))},
+        "bank_build_s": build_s,
+        "bank_bytes": info["bank_bytes"],
+        "tails_per_step": n_tails,
+    }
+    if not args.no_fp16 and args.precision == "f32":
+        wall16, build16, corr16, lat16, _, info16 = run_plan(bfs, torch, w, y_dev, "f32-w16f",
+                                                             args.steps, args.warmup)
+        line["fp16_spectra"] = {"value": args.steps * k / wall16, "kernel_rate": k / (np.mean(corr16) * 1e-3),
+                                "ms_per_step": wall16 / args.steps * 1e3, "bank_build_s": build16,
+                                "bank_bytes": info16["bank_bytes"]}
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        c = torch.empty_like(a)
+        for _ in range(3):
+            c.copy_(a)
+        torch.cuda.synchronize()
+        line["copy_calibration_bytes"] = nbytes
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, y, args.cpu_templates)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * bfsearch.h -- C ABI of the MI355X matched-filter hot path of butterfly
+ * filtering (van Putten, "Deep searches for broadband extended
+ * gravitational-wave emission bursts by heterogeneous computing",
+ * arXiv:1708.01609).
+ *
+ * Problem statement (Sec. 3): a real strain segment y of N samples is
+ * correlated against a bank of real chirp templates w_j (Eq. 3), evaluated by
+ * the three-step FFT correlation of Eq. (5): forward real FFTs, the product
+ * conj(W) * Y, an inverse FFT.  Each correlation's standard deviation sigma
+ * (Eq. 6) is predicted from the spectrum by Parseval's theorem (Eq. 7) before
+ * the inverse transform, and only the tails |rho_n| > kappa * sigma (Eq. 9,
+ * on the absolute value) are compacted on the device and returned to the host
+ * (Sec. 3.2-3.3, "gather all hits" mode).
+ *
+ * Conventions fixed by this library:
+ *   rho_sj[n] = sum_{m<L} w_j[m] * y_s[(n + m) mod N],  n = 0..N-1
+ *     (circular: the template is zero-padded to N, Sec. 3.2 step (ii)),
+ *   sigma_sj  = sqrt(sum_n rho_sj[n]^2 / N)      (Eq. 6, RMS about zero),
+ *   computed as (1/N) sqrt(|C_0|^2 + |C_{N/2}|^2 + 2 sum_{k=1}^{N/2-1} |C_k|^2)
+ *     with C = conj(W) Y (the exact form of Eq. 7 for any real input),
+ *   tail = (s, j, n, rho) for every |rho_sj[n]| > kappa * sigma_sj (strict).
+ *   Grid templates: w_j[m] = h[m] cos(2 pi (f0 t + fdot t^2 / 2)), t = m/fs,
+ *   h the symmetric Hann window, normalised to sum w^2 = 1; template id
+ *   j = i_f0 * n_fdot + i_fdot over inclusive linspace grids; duration
+ *   tau[j % n_tau], L = nearest integer to tau * fs (ties to even).
+ *
+ * Errors: every call returns a bfs_status; nothing throws across the ABI.
+ * Argument checks happen before any HIP call, so an invalid call returns
+ * BFS_ERR_INVALID_ARG without touching the device.
+ *
+ * Threading: a plan is immutable after bfsearch_plan and may be used by
+ * several threads issuing bfsearch_filter on different streams.  A job is
+ * used by one thread at a time.
+ */
+#ifndef BFSEARCH_H
+#define BFSEARCH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  BFS_OK = 0,
+  BFS_ERR_INVALID_ARG = -1,   /* bad descriptor, size, pointer or length */
+  BFS_ERR_OUT_OF_MEMORY = -2, /* HBM budget or device allocation exceeded; nothing kept */
+  BFS_ERR_HIP = -3,           /* a HIP runtime call failed */
+  BFS_ERR_TAIL_OVERFLOW = -4, /* more tails than capacity; totals stay exact */
+  BFS_ERR_UNSUPPORTED = -5    /* valid request outside the built kernel set */
+} bfs_status;
+
+typedef enum {
+  BFS_FP64 = 0,      /* samples, spectra and FFTs in FP64 */
+  BFS_FP32 = 1,      /* FP32 samples, spectra and FFTs; sigma and norms in FP64 */
+  BFS_FP32_W16F = 2, /* as BFS_FP32, template spectra stored as FP16 */
+  BFS_FP32_W16B = 3  /* as BFS_FP32, template spectra stored as BF16 */
+} bfs_precision;
+
+typedef struct bfs_plan bfs_plan; /* opaque: resident template bank, tables */
+typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
+
+/* One tail record (24 bytes).  rho is the correlation value rho_sj[lag] of
+ * the convention above (not divided by sigma). */
+typedef struct {
+  uint32_t segment;
+  uint32_t template_id;
+  uint32_t lag;
+  uint32_t reserved;
+  double rho;
+} bfs_tail;
+
+/* Plan descriptor.  All pointers are host memory, read during the call only. */
+typedef struct {
+  uint32_t n;                   /* segment length N: power of two, supported
+                                   2^10..2^16 (BFS_FP32*) or 2^10..2^13 (BFS_FP64) */
+  double fs;                    /* sample rate in Hz, > 0 */
+  uint32_t n_f0, n_fdot;        /* grid size; K = n_f0 * n_fdot */
+  double f0_lo, f0_hi;          /* initial frequency range (Hz), inclusive */
+  double fdot_lo, fdot_hi;      /* frequency rate range (Hz/s), inclusive */
+  uint32_t n_tau;               /* number of durations, >= 1 */
+  const double* tau;            /* [n_tau] durations in s; template j uses tau[j % n_tau] */
+  uint32_t taper;               /* 0: none, 1: symmetric Hann */
+  const double* explicit_templates; /* optional host [n_explicit][explicit_len] FP64
+                                       bank used as given (no normalisation);
+                                       when set, the grid fields are ignored */
+  uint32_t n_explicit, explicit_len;
+  double kappa;                 /* threshold multiple, >= 0 (0 keeps every nonzero lag) */
+  bfs_precision precision;
+  uint64_t tail_capacity;       /* device tail slots per job, >= 1 */
+  uint64_t hbm_budget_bytes;    /* 0: the device's free memory */
+  int device;                   /* HIP device ordinal */
+} bfs_plan_desc;
+
+/* Read-only facts about a plan. */
+typedef struct {
+  uint32_t n, m, k;             /* N, N/2, number of templates */
+  uint32_t threads_per_correlation;
+  uint64_t bank_bytes;          /* resident template spectra */
+  uint64_t plan_bytes;          /* all device memory held by the plan */
+  uint32_t precision;
+  uint32_t reserved;
+} bfs_plan_info;
+
+/* Build a plan: synthesises every template on the device (FP64 phase and
+ * norm), transforms it (real FFT of the template zero-padded to N, Sec. 3.2
+ * step (ii)) and keeps the spectra resident in HBM.  On error *out is NULL
+ * and nothing stays allocated. */
+bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
+
+/* Queue the hot path for n_segments segments on hip_stream (a hipStream_t;
+ * NULL = the null stream) and return at once.
+ *   y_dev: caller-owned device memory, n_segments * N samples, segment s at
+ *          y_dev + s * N; double for BFS_FP64 plans, float otherwise.  It must
+ *          stay valid until the job has been fetched or released.
+ * Per segment: forward real FFT of y (Eq. 5); then per template one fused
+ * kernel computes C = conj(W) Y, sigma by Parseval in FP64 (Eq. 7), the
+ * inverse FFT on chip (Eq. 5), the threshold (Eq. 9) and wave-ballot
+ * compaction of the tails into the job's device buffer. */
+bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, uint32_t n_segments,
+                           void* hip_stream, bfs_job** out);
+
+/* Wait for the job, copy its tails to out_host sorted by (segment,
+ * template_id, lag), and report counts.
+ *   capacity: slots in out_host; *n_written <= capacity; *n_total = exact
+ *   number of tails the kernels found.  Returns BFS_ERR_TAIL_OVERFLOW when
+ *   *n_total exceeds capacity or the plan's tail_capacity; the records then
+ *   written are an arbitrary subset. */
+bfs_status bfsearch_fetch_tails(bfs_job* job, bfs_tail* out_host, uint64_t capacity,
+                                uint64_t* n_written, uint64_t* n_total);
+
+/* Wait for the job and copy sigma[s][j] (FP64, Eq. 6 by Parseval) to out_host
+ * ([n_segments][K] doubles). */
+bfs_status bfsearch_fetch_sigma(bfs_job* job, double* out_host);
+
+/* Device time of the job's kernels in milliseconds, measured with HIP events
+ * on the job's stream: *corr_ms brackets the fused correlation kernel,
+ * *total_ms the whole job.  Waits for the job. */
+bfs_status bfsearch_job_timing(bfs_job* job, float* corr_ms, float* total_ms);
+
+/* Return the job's buffers to the plan.  The job pointer is invalid after. */
+bfs_status bfsearch_job_release(bfs_job* job);
+
+/* Free a plan.  All its jobs must have been released. */
+bfs_status bfsearch_destroy(bfs_plan* plan);
+
+bfs_status bfsearch_plan_get_info(const bfs_plan* plan, bfs_plan_info* out);
+
+/* Diagnostic: the same fused kernel, writing every rho value instead of
+ * compacting tails.  rho_dev: caller device memory [n_segments][K][N] of the
+ * plan's sample type (double or float); sigma_dev: [n_segments][K] doubles
+ * (may be NULL).  Queued on hip_stream; no host synchronisation. */
+bfs_status bfsearch_correlate_dense(bfs_plan* plan, const void* y_dev, uint32_t n_segments,
+                                    void* rho_dev, double* sigma_dev, void* hip_stream);
+
+/* Diagnostic: template spectra W_j[k], k = 0..N/2, as interleaved FP64
+ * complex into caller device memory out_dev [count][N/2 + 1][2], for
+ * templates first..first+count-1.  Queued on hip_stream. */
+bfs_status bfsearch_plan_spectra(const bfs_plan* plan, uint32_t first, uint32_t count,
+                                 double* out_dev, void* hip_stream);
+
+/* Diagnostic: the job's segment spectra Y_s[k], k = 0..N/2, as interleaved
+ * FP64 complex into out_dev [n_segments][N/2 + 1][2].  Queued on the job's
+ * stream. */
+bfs_status bfsearch_job_spectra(const bfs_job* job, double* out_dev);
+
+const char* bfsearch_status_string(bfs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BFSEARCH_H */

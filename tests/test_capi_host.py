@@ -1,0 +1,123 @@
+"""C-ABI checks that need no GPU: exported symbols and host-side argument validation.
+
+Every invalid call below must be rejected before the library makes any HIP
+call, so these run on a machine without a GPU.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bfsearch.h")
+
+
+@pytest.fixture(scope="module")
+def bfs():
+    from paper_1708_01609_amd import build as b
+
+    if not os.path.exists(b.LIB):
+        b.build()
+    from paper_1708_01609_amd import bfsearch
+
+    return bfsearch
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:bfs_status|const char\*)\s+(bfsearch_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("bfsearch_plan", "bfsearch_filter", "bfsearch_fetch_tails", "bfsearch_fetch_sigma",
+                     "bfsearch_job_release", "bfsearch_destroy", "bfsearch_status_string"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(bfs):
+    lib = bfs.raw_library()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_struct_layouts_match_header(bfs):
+    assert ctypes.sizeof(bfs.PlanInfo) == 40
+    assert bfs.TAIL_DTYPE.itemsize == 24
+    # bfs_plan_desc field order as declared (spot-check offsets of the 64-bit fields)
+    assert bfs.PlanDesc.fs.offset == 8
+    assert bfs.PlanDesc.tail_capacity.offset % 8 == 0
+
+
+def test_status_strings(bfs):
+    assert bfs.status_string(0) == "ok"
+    assert "overflow" in bfs.status_string(-4)
+    assert bfs.status_string(-99) == "unknown status"
+
+
+def _desc(bfs, **kw):
+    d = bfs.PlanDesc()
+    taus = np.array([1.0])
+    d.n, d.fs, d.n_f0, d.n_fdot = 1 << 16, 4096.0, 4, 4
+    d.f0_lo, d.f0_hi, d.fdot_lo, d.fdot_hi = 350.0, 2000.0, -500.0, 500.0
+    d.n_tau = 1
+    d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.taper, d.kappa, d.precision, d.tail_capacity = 1, 5.0, bfs.FP32, 1024
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d, taus
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 1000),            # not a power of two
+    ("n", 0),
+    ("fs", 0.0),
+    ("fs", -1.0),
+    ("kappa", -1.0),
+    ("tail_capacity", 0),
+    ("precision", 7),
+    ("taper", 2),
+    ("n_f0", 0),
+    ("n_tau", 0),
+    ("fdot_hi", float("nan")),
+])
+def test_plan_rejects_invalid_descriptor(bfs, field, value):
+    d, keep = _desc(bfs, **{field: value})
+    out = ctypes.c_void_p(1)
+    st = bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out))
+    assert st == bfs.BFS_ERR_INVALID_ARG
+    assert not out.value
+
+
+def test_plan_rejects_template_longer_than_segment(bfs):
+    taus = np.array([2.0])  # 8192 samples > N = 4096
+    d, _ = _desc(bfs, n=4096)
+    d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    out = ctypes.c_void_p()
+    assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+
+
+def test_plan_reports_unsupported_sizes(bfs):
+    for n, prec in ((1 << 17, bfs.FP32), (1 << 14, bfs.FP64), (1 << 9, bfs.FP32)):
+        d, keep = _desc(bfs, n=n, precision=prec)
+        taus = np.array([0.1])
+        d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out = ctypes.c_void_p()
+        assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_UNSUPPORTED
+
+
+def test_null_handles_are_rejected(bfs):
+    lib = bfs.raw_library()
+    out = ctypes.c_void_p()
+    nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.bfsearch_plan(None, ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_filter(None, None, 1, None, ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_fetch_tails(None, None, 0, ctypes.byref(nw), ctypes.byref(nt)) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_fetch_sigma(None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_job_release(None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_destroy(None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_correlate_dense(None, None, 1, None, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_plan_spectra(None, 0, 1, None, None) == bfs.BFS_ERR_INVALID_ARG
