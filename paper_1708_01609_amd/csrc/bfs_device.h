@@ -200,6 +200,36 @@ __device__ __forceinline__ void buf_store(V v, rsrc_t r, uint32_t voff, uint32_t
 }
 
 // ------------------------------------------------------------------------
+// Cross-half lane exchange.  v_permlane32_swap(D, S) swaps the upper 32
+// lanes of D with the lower 32 lanes of S, i.e. D' = {D.lo, S.lo},
+// S' = {D.hi, S.hi}.  Applied to (a, b) and then to (S', D') it yields
+// {a.hi, a.lo} and {b.hi, b.lo}: each register with its halves exchanged,
+// which is the value lane l ^ 32 holds.  Two swaps serve two registers.
+__device__ __forceinline__ void halfswap2(uint32_t a, uint32_t b, uint32_t& sa, uint32_t& sb) {
+  const auto r1 = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  const auto r2 = __builtin_amdgcn_permlane32_swap(r1[1], r1[0], false, false);
+  sa = r2[0];
+  sb = r2[1];
+}
+// pa = b and pb = a as held by lane l ^ 32 (complex, any real type)
+template <typename T>
+__device__ __forceinline__ void partner_pair(const cx<T>& a, const cx<T>& b, cx<T>& pa, cx<T>& pb) {
+  constexpr int W = sizeof(cx<T>) / 4;
+  const auto ua = __builtin_bit_cast(typename std::conditional<W == 2, u32x2, u32x4>::type, a);
+  const auto ub = __builtin_bit_cast(typename std::conditional<W == 2, u32x2, u32x4>::type, b);
+  typename std::conditional<W == 2, u32x2, u32x4>::type sa, sb;
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    uint32_t x, y;
+    halfswap2(ua[i], ub[i], x, y);
+    sa[i] = x;
+    sb[i] = y;
+  }
+  pb = __builtin_bit_cast(cx<T>, sa);
+  pa = __builtin_bit_cast(cx<T>, sb);
+}
+
+// ------------------------------------------------------------------------
 // Wave64 helpers.
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll

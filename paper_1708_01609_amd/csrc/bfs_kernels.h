@@ -232,43 +232,28 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   cx<T> v[F::P];
   double acc = 0.0;
 
-  // ---- spectral product, Parseval partial sum, Hermitian repack.
-  // Element (col, k2) is k = col + S1 k2 with partner p = M - k (mod M; slot 0
-  // packs C_0 and C_M).  exp(2 pi i k / N) = exp(2 pi i col / N) *
-  // exp(i pi k2 / R1): one table load per column, a constant rotation per
-  // element.  Loads run one group of G elements ahead of the arithmetic.
+  // ---- spectral product and Parseval partial sum.  Element (col, k2) is
+  // k = col + S1 k2; slot 0 of thread 0 packs the real C_0 (x) and C_M (y).
+  // The loads run one group of G elements ahead of the arithmetic.
   constexpr int G = 2, NG = F::R1 / G;
-  static_assert(F::R1 % G == 0, "group size");
+  static_assert(F::R1 % G == 0 && F::R1 % 2 == 0, "group size");
+  constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
   uint32_t cols[F::C1];
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, true>(t, c);
+  T cM = T(0);  // C_M of thread 0 (real)
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
     const uint32_t col = cols[c];
-    const bool dc = (c == 0) && (col == 0u);  // slot 0 packs the real C_0 (x) and C_M (y)
-    const cx<T> bu = tw_u[col];
-    TW lwk[2][G], lwp[2][G];
-    cx<T> lyk[2][G], lyp[2][G];
-    // k = col + S1 k2 and, for k2 >= 1, p = (M - S1 (k2+1)) + (S1 - col): the
-    // k2-dependent part is a uniform base (scalar registers), the per-lane
-    // part one offset, so no per-element address stays live
-    constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
-    const uint32_t pcol = uint32_t(F::S1) - col;
-    const uint32_t p0 = (uint32_t(M) - col) & uint32_t(M - 1);
+    const bool dc = (c == 0) && (col == 0u);
+    TW lw[2][G];
+    cx<T> ly[2][G];
     auto issue = [&](int g, int buf) {
 #pragma unroll
       for (int e = 0; e < G; ++e) {
         const uint32_t k2 = uint32_t(g * G + e);
-        lwk[buf][e] = buf_load<TW>(rW, col * SW, uint32_t(F::S1) * k2 * SW);
-        lyk[buf][e] = buf_load<cx<T>>(rY, col * SY, uint32_t(F::S1) * k2 * SY);
-        if (k2 == 0) {
-          lwp[buf][e] = buf_load<TW>(rW, p0 * SW, 0u);
-          lyp[buf][e] = buf_load<cx<T>>(rY, p0 * SY, 0u);
-        } else {
-          const uint32_t base = uint32_t(M) - uint32_t(F::S1) * (k2 + 1);
-          lwp[buf][e] = buf_load<TW>(rW, pcol * SW, base * SW);
-          lyp[buf][e] = buf_load<cx<T>>(rY, pcol * SY, base * SY);
-        }
+        lw[buf][e] = buf_load<TW>(rW, col * SW, uint32_t(F::S1) * k2 * SW);
+        ly[buf][e] = buf_load<cx<T>>(rY, col * SY, uint32_t(F::S1) * k2 * SY);
       }
     };
     issue(0, 0);
@@ -278,34 +263,69 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
       static_for<G>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
         constexpr int k2 = g * G + e;
-        cx<T> wk = load_spec<TW, T>(&lwk[g & 1][e], 0), yk = lyk[g & 1][e];
-        cx<T> wp = load_spec<TW, T>(&lwp[g & 1][e], 0), yp = lyp[g & 1][e];
+        cx<T> wk = load_spec<TW, T>(&lw[g & 1][e], 0), yk = ly[g & 1][e];
         if constexpr (k2 == 0) {
-          // DC element: own = (W_0, 0)(Y_0, 0), partner = (W_M, 0)(Y_M, 0)
+          if (c == 0) cM = dc ? wk.y * yk.y : T(0);
           wk.y = dc ? T(0) : wk.y;
           yk.y = dc ? T(0) : yk.y;
-          wp.x = dc ? wp.y : wp.x;
-          yp.x = dc ? yp.y : yp.x;
-          wp.y = dc ? T(0) : wp.y;
-          yp.y = dc ? T(0) : yp.y;
         }
         const cx<T> ck = cmulc(wk, yk);
-        const cx<T> cp = cmulc(wp, yp);
         double pk = 2.0 * (double(ck.x) * double(ck.x) + double(ck.y) * double(ck.y));
         if constexpr (k2 == 0) {
-          const double pdc = double(ck.x) * double(ck.x) + double(cp.x) * double(cp.x);
+          const double pdc = double(ck.x) * double(ck.x) + double(cM) * double(cM);
           pk = dc ? pdc : pk;
         }
         acc += pk;
-        const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
-        const cx<T> bq = {ck.x - cp.x, ck.y + cp.y};  // C_k - conj C_{M-k}
-        const cx<T> u = cmul(rot<k2, 2 * F::R1, +1>(bu), bq);
-        v[c * F::R1 + k2] = {a.x - u.y, a.y + u.x};
+        v[c * F::R1 + k2] = ck;
         pin(v[c * F::R1 + k2]);
       });
       pin(acc);
       sched_fence();
     });
+  }
+
+  // ---- Hermitian repack for the length-M inverse transform:
+  //   Z_k = (C_k + conj C_{M-k}) + i exp(+2 pi i k / N) (C_k - conj C_{M-k}).
+  // The partner of (col, k2) is (S1 - col, R1-1-k2), held by lane l ^ 32 of the
+  // same wave at register R1-1-k2 (mirror column map), so registers k2 and
+  // R1-1-k2 swap halves as a pair.  Columns 0 and S1/2 (lanes 0 and 32 of
+  // wave 0) pair inside their own column: col 0 with index (R1 - k2) mod R1
+  // (k2 = 0 with C_M), col S1/2 with R1-1-k2.  exp(2 pi i k / N) =
+  // exp(2 pi i col / N) exp(i pi k2 / R1): one table load per column.
+  const int lane = t & 63;
+  const bool wave0 = t < 64;
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) {
+    const cx<T> bu = tw_u[cols[c]];
+    cx<T> carry = {T(0), T(0)};
+    static_for<F::R1 / 2>([&](auto kc) {
+      constexpr int r1 = decltype(kc)::value;
+      constexpr int r2 = F::R1 - 1 - r1;
+      const cx<T> A = v[c * F::R1 + r1], B = v[c * F::R1 + r2];
+      cx<T> PA, PB;
+      partner_pair(A, B, PA, PB);
+      if (c == 0 && wave0) {
+        const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
+        const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
+        PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
+        PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
+        PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
+        PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
+        carry = B;
+      }
+      auto repack = [&](const cx<T>& ck, const cx<T>& cp, const cx<T>& tk) {
+        const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
+        const cx<T> bq = {ck.x - cp.x, ck.y + cp.y};  // C_k - conj C_{M-k}
+        const cx<T> u = cmul(tk, bq);
+        return cx<T>{a.x - u.y, a.y + u.x};
+      };
+      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(bu));
+      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(bu));
+      pin(v[c * F::R1 + r1]);
+      pin(v[c * F::R1 + r2]);
+      if constexpr (r1 % 4 == 3) sched_fence();
+    });
+    sched_fence();
   }
 
   fft3_pass1<F, +1>(v, tw1, cols);

@@ -13,7 +13,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/bfsearch.h"
+#include "bfsearch.h"
 #include "bfs_kernels.h"
 
 using namespace bfs;
