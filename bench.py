@@ -27,6 +27,25 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
+# HBM bytes per corr_kernel launch on the C2 workload, from rocprofv3 FETCH_SIZE (x2, the
+# factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
+# for the kernel sources they were taken on (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
+MEASURED_TRAFFIC = {
+    "592dd8c611d975a5": {"f32": 2.1941e9, "f32-w16f": 1.0845e9},
+}
+
+
+def kernel_source_hash() -> str:
+    import glob
+    import hashlib
+
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1708_01609_amd", "csrc")
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def nominal_flops(n: int) -> float:
     """5 N log2 N per correlation: the paper's FFT cost convention (Eq. 10, Sec. 3.2)."""
@@ -163,7 +182,8 @@ def main():
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_VECTOR,
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(args.precision)
+            if w.name == "C2" else None,
             "flops_per_correlation": algorithmic_flops(w.n),
             "correlations_per_launch": k,
             "kernel_ms_avg": corr_avg_s * 1e3,
@@ -184,13 +204,15 @@ def main():
                                 "ms_per_step": wall16 / args.steps * 1e3, "bank_build_s": build16,
                                 "bank_bytes": info16["bank_bytes"]}
     if args.copy_calibration_mib:
+        # plain kernels of known traffic for scaling the HBM counters: fill writes X bytes,
+        # neg reads X and writes X, sum reads X
         nbytes = args.copy_calibration_mib << 20
         a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0").fill_(1.0)
         c = torch.empty_like(a)
-        for _ in range(3):
-            c.copy_(a)
+        torch.neg(a, out=c)
+        _ = float(a.sum())
         torch.cuda.synchronize()
-        line["copy_calibration_bytes"] = nbytes
+        line["calibration_bytes"] = nbytes
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, y, args.cpu_templates)
     print(json.dumps(line), flush=True)
