@@ -9,7 +9,12 @@ paper loads precomputed template transforms (Sec. 3.2, step (ii)); its build
 time is reported beside the step rate.
 
 Prints one JSON line.  With no flags: N = 1 GPU, workload C2 (N = 2^16,
-8192 one-second chirps, kappa = 5, FP32), 20 timed steps after 3 warmups.
+8192 one-second chirps, kappa = 5, FP32), 20 timed steps after 3 warmups;
+beside it the same with FP16-stored spectra, the batched form (C4: 64
+segments of 2^14..2^17 samples against 65,536 chirps in one graph-replayed
+job per step, autotuned kernels) and the serving form (C5: Poisson arrivals
+of mixed-length segments against 262,144 FP16 chirp spectra, continuous
+batching over several streams, p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -76,6 +81,16 @@ def parse():
                    help="templates in the bounded oracle sample")
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="also run a plain torch copy of this size (HBM counter calibration)")
+    p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-serving", action="store_true")
+    p.add_argument("--batched-steps", type=int, default=5)
+    p.add_argument("--serve-seconds", type=float, default=30.0,
+                   help="simulated seconds of the C5 stream replayed at 1x for latency")
+    p.add_argument("--serve-compressed-seconds", type=float, default=60.0,
+                   help="simulated seconds of the C5 stream replayed as fast as arrivals allow")
+    p.add_argument("--serve-speed", type=float, default=50.0)
+    p.add_argument("--slots", type=int, default=4)
+    p.add_argument("--max-batch", type=int, default=8)
     return p.parse_args()
 
 
@@ -104,6 +119,85 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup):
     info = {"bank_bytes": plan.bank_bytes, "threads": plan.threads_per_correlation}
     plan.close()
     return wall, build_s, corr_ms, lat_ms, n_tails, info
+
+
+def run_batched(bfs, torch, steps, warmup):
+    """C4: 64 segments of 2^14..2^17 samples, 65,536 chirps (tau 0.5/1/2 s), FP32, one filter call
+    per step, captured once as a HIP graph and replayed, kernels autotuned at plan time."""
+    import numpy as np
+    from synthetic import get_workload, make_segment
+
+    w = get_workload("C4")
+    segs = [make_segment(w, s)[0] for s in range(w.n_segments)]
+    lens = [len(y) for y in segs]
+    flat = torch.from_numpy(np.concatenate(segs).astype(np.float32)).cuda()
+    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
+    t0 = time.perf_counter()
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision="f32", n_min=min(w.lengths),
+                    graph=True, autotune=True)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        with plan.filter(flat, lengths=lens) as job:
+            job.fetch_tails()
+    torch.cuda.synchronize()
+    graph_ms, tails = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        job = plan.filter(flat, lengths=lens)
+        tails = job.fetch_tails()[1]
+        graph_ms.append(job.timing()[0])
+        job.release()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k = w.n_templates
+    corr = k * len(segs)
+    flops = sum(algorithmic_flops(n) for n in lens) * k
+    kernels = {str(n): plan.kernel_info(n) for n in sorted(set(lens))}
+    out = {"workload": f"C4: {w.description}", "value": steps * corr / wall, "unit": "correlations/s",
+           "ms_per_step": wall / steps * 1e3, "graph_replay_ms": float(np.mean(graph_ms)),
+           "correlations_per_step": corr, "segment_lengths": {str(n): lens.count(n) for n in sorted(set(lens))},
+           "achieved_tflops_algorithmic": flops / (np.mean(graph_ms) * 1e-3) / 1e12,
+           "frac_of_fp32_vector_peak": flops / (np.mean(graph_ms) * 1e-3) / PEAK_FP32_VECTOR,
+           "bank_bytes": plan.bank_bytes, "bank_build_and_tune_s": build_s, "tails_per_step": tails,
+           "kernels": kernels}
+    plan.close()
+    return out
+
+
+def run_serving(bfs, torch, args):
+    """C5: Poisson arrivals (8/s, 4 channels) of 2^14..2^17-sample segments against 262,144
+    one-second chirps with FP16 spectra; continuous batching over several streams with HBM-budget
+    admission.  A 1x replay gives the latency; a compressed replay the sustained rate under load."""
+    from paper_1708_01609_amd.serve import GpuExecutor, Request, serve
+    from synthetic import arrivals, get_workload, request_samples
+
+    w = get_workload("C5")
+    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
+    t0 = time.perf_counter()
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision="f32-w16f", n_min=min(w.lengths),
+                    autotune=True)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    horizon = max(args.serve_seconds, args.serve_compressed_seconds)
+    arr = arrivals(w, horizon)
+    reqs = [Request(a.index, a.time, request_samples(w, a)[0], a.channel) for a in arr]
+    ex = GpuExecutor(plan, slots=args.slots, max_batch=args.max_batch)
+    budget = args.slots * plan.job_bytes([w.n] * args.max_batch)
+    # warm the executor's streams and the job-buffer pool
+    serve(ex, reqs[: 2 * args.max_batch], slots=args.slots, max_batch=args.max_batch, budget_bytes=budget,
+          speed=1e6)
+    rt = serve(ex, [r for r in reqs if r.arrival < args.serve_seconds], slots=args.slots,
+               max_batch=args.max_batch, budget_bytes=budget, speed=1.0)
+    sat = serve(ex, [r for r in reqs if r.arrival < args.serve_compressed_seconds], slots=args.slots,
+                max_batch=args.max_batch, budget_bytes=budget, speed=args.serve_speed)
+    k = w.n_templates
+    out = {"workload": f"C5: {w.description}", "bank_bytes": plan.bank_bytes, "bank_build_and_tune_s": build_s,
+           "slots": args.slots, "max_batch": args.max_batch, "hbm_budget_bytes_jobs": budget,
+           "realtime": dict(rt.summary(k), simulated_s=args.serve_seconds, speed=1.0),
+           "compressed": dict(sat.summary(k), simulated_s=args.serve_compressed_seconds, speed=args.serve_speed)}
+    plan.close()
+    return out
 
 
 def cpu_baseline(w, y, n_templates):
@@ -213,6 +307,10 @@ def main():
         _ = float(a.sum())
         torch.cuda.synchronize()
         line["calibration_bytes"] = nbytes
+    if not args.no_batched and args.workload == "C2":
+        line["batched"] = run_batched(bfs, torch, args.batched_steps, 1)
+    if not args.no_serving and args.workload == "C2":
+        line["serving"] = run_serving(bfs, torch, args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, y, args.cpu_templates)
     print(json.dumps(line), flush=True)

@@ -58,7 +58,14 @@ typedef enum {
   BFS_FP32_W16B = 3  /* as BFS_FP32, template spectra stored as BF16 */
 } bfs_precision;
 
-typedef struct bfs_plan bfs_plan; /* opaque: resident template bank, tables */
+/* Plan flags. */
+#define BFS_PLAN_GRAPH 1u    /* capture each job shape once as a HIP graph and
+                                replay it (fewer launches per filter call) */
+#define BFS_PLAN_AUTOTUNE 2u /* at plan time, time every kernel candidate of
+                                each segment length on the resident bank and
+                                keep the fastest (default: the first) */
+
+typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
 
 /* One tail record (24 bytes).  rho is the correlation value rho_sj[lag] of
@@ -73,53 +80,88 @@ typedef struct {
 
 /* Plan descriptor.  All pointers are host memory, read during the call only. */
 typedef struct {
-  uint32_t n;                   /* segment length N: power of two, supported
-                                   2^10..2^16 (BFS_FP32*) or 2^10..2^13 (BFS_FP64) */
+  uint32_t n;                   /* largest segment length N: power of two, supported
+                                   2^10..2^17 (BFS_FP32*) or 2^10..2^14 (BFS_FP64) */
+  uint32_t n_min;               /* smallest segment length (power of two <= n;
+                                   0 = n).  The plan keeps one resident bank per
+                                   power of two in [n_min, n] (each template
+                                   zero-padded to that length), so segments of
+                                   every such length can share a filter call */
   double fs;                    /* sample rate in Hz, > 0 */
   uint32_t n_f0, n_fdot;        /* grid size; K = n_f0 * n_fdot */
   double f0_lo, f0_hi;          /* initial frequency range (Hz), inclusive */
   double fdot_lo, fdot_hi;      /* frequency rate range (Hz/s), inclusive */
   uint32_t n_tau;               /* number of durations, >= 1 */
-  const double* tau;            /* [n_tau] durations in s; template j uses tau[j % n_tau] */
+  const double* tau;            /* [n_tau] durations in s; template j uses tau[j % n_tau];
+                                   every L = round(tau * fs) must be <= n_min */
   uint32_t taper;               /* 0: none, 1: symmetric Hann */
   const double* explicit_templates; /* optional host [n_explicit][explicit_len] FP64
                                        bank used as given (no normalisation);
-                                       when set, the grid fields are ignored */
+                                       when set, the grid fields are ignored;
+                                       explicit_len <= n_min */
   uint32_t n_explicit, explicit_len;
   double kappa;                 /* threshold multiple, >= 0 (0 keeps every nonzero lag) */
   bfs_precision precision;
   uint64_t tail_capacity;       /* device tail slots per job, >= 1 */
-  uint64_t hbm_budget_bytes;    /* 0: the device's free memory */
+  uint64_t hbm_budget_bytes;    /* 0: the device's free memory.  Plan memory
+                                   (banks, tables) and every live job's buffers
+                                   count against it; a call that would exceed it
+                                   fails with BFS_ERR_OUT_OF_MEMORY */
   int device;                   /* HIP device ordinal */
+  uint32_t flags;               /* BFS_PLAN_* bits, 0 for none */
+  uint32_t candidate;           /* 0: the default kernel (or the autotuned
+                                   one); i > 0: candidate i - 1 at every length
+                                   that has that many (manual tuning, tests) */
 } bfs_plan_desc;
 
 /* Read-only facts about a plan. */
 typedef struct {
-  uint32_t n, m, k;             /* N, N/2, number of templates */
-  uint32_t threads_per_correlation;
-  uint64_t bank_bytes;          /* resident template spectra */
+  uint32_t n, m, k;             /* largest N, N/2, number of templates */
+  uint32_t threads_per_correlation; /* workgroup size of the fused kernel at N */
+  uint64_t bank_bytes;          /* resident template spectra, all lengths */
   uint64_t plan_bytes;          /* all device memory held by the plan */
   uint32_t precision;
-  uint32_t reserved;
+  uint32_t n_min;               /* smallest accepted segment length */
 } bfs_plan_info;
 
+/* The fused kernel a plan runs at one segment length. */
+typedef struct {
+  uint32_t n;                   /* segment length */
+  uint32_t r1, r2, r3;          /* radices of the on-chip transform (length r1*r2*r3) */
+  uint32_t threads;             /* workgroup size (one correlation per workgroup) */
+  uint32_t load_group;          /* spectrum elements loaded ahead per group */
+  uint32_t split;               /* 1: the length-n/2 inverse transform runs as two halves */
+  uint32_t candidate;           /* index of the chosen candidate */
+  uint32_t n_candidates;        /* candidates built for this length */
+  float tuned_us[8];            /* per candidate: measured microseconds per
+                                   correlation (BFS_PLAN_AUTOTUNE), else 0 */
+} bfs_kernel_info;
+
 /* Build a plan: synthesises every template on the device (FP64 phase and
- * norm), transforms it (real FFT of the template zero-padded to N, Sec. 3.2
- * step (ii)) and keeps the spectra resident in HBM.  On error *out is NULL
- * and nothing stays allocated. */
+ * norm), transforms it (real FFT of the template zero-padded to each
+ * accepted length, Sec. 3.2 step (ii)) and keeps the spectra resident in
+ * HBM.  On error *out is NULL and nothing stays allocated. */
 bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
 
 /* Queue the hot path for n_segments segments on hip_stream (a hipStream_t;
  * NULL = the null stream) and return at once.
- *   y_dev: caller-owned device memory, n_segments * N samples, segment s at
- *          y_dev + s * N; double for BFS_FP64 plans, float otherwise.  It must
- *          stay valid until the job has been fetched or released.
- * Per segment: forward real FFT of y (Eq. 5); then per template one fused
- * kernel computes C = conj(W) Y, sigma by Parseval in FP64 (Eq. 7), the
- * inverse FFT on chip (Eq. 5), the threshold (Eq. 9) and wave-ballot
- * compaction of the tails into the job's device buffer. */
-bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, uint32_t n_segments,
-                           void* hip_stream, bfs_job** out);
+ *   y_dev: caller-owned device memory holding the samples; double for
+ *          BFS_FP64 plans, float otherwise.  It must stay valid until the
+ *          job's kernels have finished (fetch, timing or release).
+ *   seg_lengths: host [n_segments], each a power of two in [n_min, n]; NULL
+ *          means every segment has length n.
+ *   seg_offsets: host [n_segments], element offset of each segment from
+ *          y_dev; NULL means the segments are packed back to back in order.
+ *   n_segments: 1..65535.
+ * Segments of one length form a group.  Per group: forward real FFT of each
+ * segment (Eq. 5); then one fused kernel per (template, segment) computes
+ * C = conj(W) Y, sigma by Parseval in FP64 (Eq. 7), the inverse FFT on chip
+ * (Eq. 5), the threshold (Eq. 9) and wave-ballot compaction of the tails into
+ * the job's device buffer.  Segment ids in tails and sigma are the indices
+ * into the caller's arrays.  The segment table is read before return. */
+bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* seg_offsets,
+                           const uint32_t* seg_lengths, uint32_t n_segments, void* hip_stream,
+                           bfs_job** out);
 
 /* Wait for the job, copy its tails to out_host sorted by (segment,
  * template_id, lag), and report counts.
@@ -135,9 +177,21 @@ bfs_status bfsearch_fetch_tails(bfs_job* job, bfs_tail* out_host, uint64_t capac
 bfs_status bfsearch_fetch_sigma(bfs_job* job, double* out_host);
 
 /* Device time of the job's kernels in milliseconds, measured with HIP events
- * on the job's stream: *corr_ms brackets the fused correlation kernel,
- * *total_ms the whole job.  Waits for the job. */
+ * on the job's stream: *corr_ms brackets the fused correlation kernels (the
+ * whole replayed graph for BFS_PLAN_GRAPH plans), *total_ms the whole job.
+ * Waits for the job. */
 bfs_status bfsearch_job_timing(bfs_job* job, float* corr_ms, float* total_ms);
+
+/* Non-blocking completion check: *done = 1 once every kernel of the job has
+ * finished, else 0. */
+bfs_status bfsearch_job_poll(bfs_job* job, int* done);
+
+/* Device bytes a filter call with these segment lengths (NULL = all n) takes
+ * from the plan's HBM budget while its job is live (segment spectra,
+ * transform scratch, sigma, tail buffer, segment table).  No device access;
+ * lets a scheduler admit work by budget before calling bfsearch_filter. */
+bfs_status bfsearch_plan_job_bytes(const bfs_plan* plan, const uint32_t* seg_lengths, uint32_t n_segments,
+                                   uint64_t* bytes);
 
 /* Return the job's buffers to the plan.  The job pointer is invalid after. */
 bfs_status bfsearch_job_release(bfs_job* job);
@@ -147,22 +201,30 @@ bfs_status bfsearch_destroy(bfs_plan* plan);
 
 bfs_status bfsearch_plan_get_info(const bfs_plan* plan, bfs_plan_info* out);
 
+/* The kernel configuration the plan uses at segment length n (0 = the
+ * largest); BFS_ERR_INVALID_ARG for a length the plan does not hold. */
+bfs_status bfsearch_plan_kernel_info(const bfs_plan* plan, uint32_t n, bfs_kernel_info* out);
+
 /* Diagnostic: the same fused kernel, writing every rho value instead of
- * compacting tails.  rho_dev: caller device memory [n_segments][K][N] of the
- * plan's sample type (double or float); sigma_dev: [n_segments][K] doubles
- * (may be NULL).  Queued on hip_stream; no host synchronisation. */
-bfs_status bfsearch_correlate_dense(bfs_plan* plan, const void* y_dev, uint32_t n_segments,
+ * compacting tails, for n_segments segments of length seg_len (0 = n)
+ * packed back to back at y_dev.  rho_dev: caller device memory
+ * [n_segments][K][seg_len] of the plan's sample type (double or float);
+ * sigma_dev: [n_segments][K] doubles (may be NULL).  Returns after the
+ * kernels finish. */
+bfs_status bfsearch_correlate_dense(bfs_plan* plan, const void* y_dev, uint32_t seg_len, uint32_t n_segments,
                                     void* rho_dev, double* sigma_dev, void* hip_stream);
 
-/* Diagnostic: template spectra W_j[k], k = 0..N/2, as interleaved FP64
- * complex into caller device memory out_dev [count][N/2 + 1][2], for
- * templates first..first+count-1.  Queued on hip_stream. */
-bfs_status bfsearch_plan_spectra(const bfs_plan* plan, uint32_t first, uint32_t count,
+/* Diagnostic: template spectra W_j[k], k = 0..n/2, at segment length n (0 =
+ * the plan's largest), as interleaved FP64 complex into caller device memory
+ * out_dev [count][n/2 + 1][2], for templates first..first+count-1.  Queued on
+ * hip_stream. */
+bfs_status bfsearch_plan_spectra(const bfs_plan* plan, uint32_t n, uint32_t first, uint32_t count,
                                  double* out_dev, void* hip_stream);
 
-/* Diagnostic: the job's segment spectra Y_s[k], k = 0..N/2, as interleaved
- * FP64 complex into out_dev [n_segments][N/2 + 1][2].  Queued on the job's
- * stream. */
+/* Diagnostic: the job's segment spectra Y_s[k], k = 0..N_s/2, as interleaved
+ * FP64 complex into out_dev, segment after segment in the caller's order
+ * (segment s starts sum_{s' < s} (N_s'/2 + 1) complex values in).  Queued on
+ * the job's stream. */
 bfs_status bfsearch_job_spectra(const bfs_job* job, double* out_dev);
 
 const char* bfsearch_status_string(bfs_status s);

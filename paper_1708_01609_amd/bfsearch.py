@@ -24,6 +24,8 @@ BFS_ERR_TAIL_OVERFLOW = -4
 BFS_ERR_UNSUPPORTED = -5
 
 FP64, FP32, FP32_W16F, FP32_W16B = 0, 1, 2, 3
+PLAN_GRAPH = 1
+PLAN_AUTOTUNE = 2
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
 TAIL_DTYPE = np.dtype(
@@ -34,6 +36,7 @@ TAIL_DTYPE = np.dtype(
 class PlanDesc(ctypes.Structure):
     _fields_ = [
         ("n", ctypes.c_uint32),
+        ("n_min", ctypes.c_uint32),
         ("fs", ctypes.c_double),
         ("n_f0", ctypes.c_uint32),
         ("n_fdot", ctypes.c_uint32),
@@ -52,6 +55,23 @@ class PlanDesc(ctypes.Structure):
         ("tail_capacity", ctypes.c_uint64),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("device", ctypes.c_int),
+        ("flags", ctypes.c_uint32),
+        ("candidate", ctypes.c_uint32),
+    ]
+
+
+class KernelInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint32),
+        ("r1", ctypes.c_uint32),
+        ("r2", ctypes.c_uint32),
+        ("r3", ctypes.c_uint32),
+        ("threads", ctypes.c_uint32),
+        ("load_group", ctypes.c_uint32),
+        ("split", ctypes.c_uint32),
+        ("candidate", ctypes.c_uint32),
+        ("n_candidates", ctypes.c_uint32),
+        ("tuned_us", ctypes.c_float * 8),
     ]
 
 
@@ -64,7 +84,7 @@ class PlanInfo(ctypes.Structure):
         ("bank_bytes", ctypes.c_uint64),
         ("plan_bytes", ctypes.c_uint64),
         ("precision", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("n_min", ctypes.c_uint32),
     ]
 
 
@@ -75,15 +95,18 @@ def _load() -> ctypes.CDLL:
     vp, u32, u64, dbl = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
     sigs = {
         "bfsearch_plan": [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)],
-        "bfsearch_filter": [vp, vp, u32, vp, ctypes.POINTER(vp)],
+        "bfsearch_filter": [vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)],
         "bfsearch_fetch_tails": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_sigma": [vp, vp],
         "bfsearch_job_timing": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "bfsearch_job_release": [vp],
+        "bfsearch_job_poll": [vp, ctypes.POINTER(ctypes.c_int)],
+        "bfsearch_plan_job_bytes": [vp, vp, u32, ctypes.POINTER(u64)],
         "bfsearch_destroy": [vp],
         "bfsearch_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
-        "bfsearch_correlate_dense": [vp, vp, u32, vp, vp, vp],
-        "bfsearch_plan_spectra": [vp, u32, u32, vp, vp],
+        "bfsearch_plan_kernel_info": [vp, u32, ctypes.POINTER(KernelInfo)],
+        "bfsearch_correlate_dense": [vp, vp, u32, u32, vp, vp, vp],
+        "bfsearch_plan_spectra": [vp, u32, u32, u32, vp, vp],
         "bfsearch_job_spectra": [vp, vp],
     }
     for name, args in sigs.items():
@@ -130,15 +153,20 @@ class Grid:
 
 
 class Plan:
-    """Resident template bank plus tables for one segment length and precision."""
+    """Resident template banks plus tables for the segment lengths n_min..n and one precision."""
 
     def __init__(self, n: int, fs: float, kappa: float, grid: Grid | None = None,
                  templates: np.ndarray | None = None, precision: str = "f32",
-                 tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0):
+                 tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
+                 n_min: int | None = None, graph: bool = False, autotune: bool = False,
+                 candidate: int = 0):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
+        d.n_min = int(n_min) if n_min else 0
         d.precision = PRECISIONS[precision]
         d.tail_capacity, d.hbm_budget_bytes, d.device = int(tail_capacity), int(hbm_budget_bytes), int(device)
+        d.flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        d.candidate = int(candidate)
         keep = []
         if templates is not None:
             t = np.ascontiguousarray(np.atleast_2d(np.asarray(templates, dtype=np.float64)))
@@ -164,53 +192,103 @@ class Plan:
         _check(_lib.bfsearch_plan(ctypes.byref(d), ctypes.byref(self._h)), "bfsearch_plan")
         info = PlanInfo()
         _check(_lib.bfsearch_plan_get_info(self._h, ctypes.byref(info)), "bfsearch_plan_get_info")
-        self.n, self.m, self.k = info.n, info.m, info.k
+        self.n, self.m, self.k, self.n_min = info.n, info.m, info.k, info.n_min
         self.threads_per_correlation = info.threads_per_correlation
         self.bank_bytes, self.plan_bytes = info.bank_bytes, info.plan_bytes
 
+    def kernel_info(self, n: int | None = None) -> dict:
+        """The fused kernel used at segment length n (default the largest): radices, workgroup
+        size, load-group depth, split, chosen candidate and (autotuned plans) us per correlation."""
+        ki = KernelInfo()
+        _check(_lib.bfsearch_plan_kernel_info(self._h, int(n or 0), ctypes.byref(ki)), "bfsearch_plan_kernel_info")
+        return {"n": ki.n, "radices": (ki.r1, ki.r2, ki.r3), "threads": ki.threads, "load_group": ki.load_group,
+                "split": bool(ki.split), "candidate": ki.candidate, "n_candidates": ki.n_candidates,
+                "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)]}
+
+    def job_bytes(self, lengths) -> int:
+        """Device bytes a filter call over segments of these lengths holds while live."""
+        lens = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint32))
+        out = ctypes.c_uint64()
+        _check(_lib.bfsearch_plan_job_bytes(self._h, ctypes.c_void_p(lens.ctypes.data), int(lens.size),
+                                            ctypes.byref(out)), "bfsearch_plan_job_bytes")
+        return int(out.value)
+
     # ---------------------------------------------------------------- filter --
-    def _segments(self, y):
+    def _check_tensor(self, y):
         import torch
 
         if not isinstance(y, torch.Tensor) or not y.is_cuda:
             raise TypeError("segments must be a CUDA tensor")
-        if y.dim() == 1:
-            y = y.unsqueeze(0)
-        if y.dim() != 2 or y.shape[1] != self.n:
-            raise ValueError(f"segments must have shape [S, {self.n}]")
         want = torch.float64 if self.sample_dtype == "float64" else torch.float32
         if y.dtype != want:
             raise TypeError(f"segments must be {want}")
-        return y.contiguous()
+        if not y.is_contiguous():
+            raise ValueError("segments must be contiguous")
+        return y
 
-    def filter(self, y, stream=None) -> "Job":
-        """Queue the hot path on `stream` (torch stream; default: current) and return the job."""
-        y = self._segments(y)
+    def _segments(self, y, n: int | None = None):
+        n = self.n if n is None else int(n)
+        y = self._check_tensor(y)
+        if y.dim() == 1:
+            y = y.unsqueeze(0)
+        if y.dim() != 2 or y.shape[1] != n:
+            raise ValueError(f"segments must have shape [S, {n}]")
+        return y
+
+    def filter(self, y, lengths=None, offsets=None, stream=None) -> "Job":
+        """Queue the hot path on `stream` (torch stream; default: current) and return the job.
+
+        y: [S, n] for segments of the plan's largest length; or, with `lengths` (one power of
+        two in [n_min, n] per segment), a flat tensor holding the segments back to back (or at
+        element `offsets`)."""
+        if lengths is None:
+            y = self._segments(y)
+            S, lens_p, offs_p, lens = y.shape[0], None, None, [self.n] * y.shape[0]
+        else:
+            y = self._check_tensor(y)
+            lens = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint32))
+            S = int(lens.size)
+            if offsets is None:
+                offs = np.concatenate([[0], np.cumsum(lens[:-1], dtype=np.uint64)]).astype(np.uint64)
+            else:
+                offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+                if offs.size != S:
+                    raise ValueError("offsets and lengths differ in size")
+            if S and int(np.max(offs + lens.astype(np.uint64))) > y.numel():
+                raise ValueError("a segment extends past the end of y")
+            keep = (lens, offs)
+            lens_p, offs_p = ctypes.c_void_p(lens.ctypes.data), ctypes.c_void_p(offs.ctypes.data)
+            lens = [int(v) for v in lens]
         h = ctypes.c_void_p()
-        _check(_lib.bfsearch_filter(self._h, ctypes.c_void_p(y.data_ptr()), y.shape[0],
+        _check(_lib.bfsearch_filter(self._h, ctypes.c_void_p(y.data_ptr()), offs_p, lens_p, S,
                                     _stream_handle(stream), ctypes.byref(h)), "bfsearch_filter")
-        return Job(self, h, y)
+        return Job(self, h, y, lens)
 
     def correlate_dense(self, y, stream=None):
-        """Diagnostic: every rho value [S, K, N] (plan sample dtype) and sigma [S, K] (float64)."""
+        """Diagnostic: every rho value [S, K, n_s] (plan sample dtype) and sigma [S, K] (float64)
+        for segments y [S, n_s] of one accepted length n_s."""
         import torch
 
-        y = self._segments(y)
-        s = y.shape[0]
-        rho = torch.empty((s, self.k, self.n), dtype=y.dtype, device=y.device)
+        y = self._check_tensor(y)
+        if y.dim() == 1:
+            y = y.unsqueeze(0)
+        s, n = y.shape
+        rho = torch.empty((s, self.k, n), dtype=y.dtype, device=y.device)
         sig = torch.empty((s, self.k), dtype=torch.float64, device=y.device)
-        _check(_lib.bfsearch_correlate_dense(self._h, ctypes.c_void_p(y.data_ptr()), s,
+        _check(_lib.bfsearch_correlate_dense(self._h, ctypes.c_void_p(y.data_ptr()), n, s,
                                              ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
                                              _stream_handle(stream)), "bfsearch_correlate_dense")
         return rho, sig
 
-    def spectra(self, first: int = 0, count: int | None = None, stream=None):
-        """Diagnostic: template spectra W_j[0..N/2] as complex128, shape [count, N/2 + 1]."""
+    def spectra(self, first: int = 0, count: int | None = None, n: int | None = None, stream=None):
+        """Diagnostic: template spectra W_j[0..n/2] at segment length n (default the largest) as
+        complex128, shape [count, n/2 + 1]."""
         import torch
 
+        n = self.n if n is None else int(n)
         count = self.k - first if count is None else count
-        out = torch.empty((count, self.m + 1, 2), dtype=torch.float64, device=f"cuda:{self.device}")
-        _check(_lib.bfsearch_plan_spectra(self._h, first, count, ctypes.c_void_p(out.data_ptr()),
+        out = torch.empty((count, n // 2 + 1, 2), dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(_lib.bfsearch_plan_spectra(self._h, n, first, count, ctypes.c_void_p(out.data_ptr()),
                                           _stream_handle(stream)), "bfsearch_plan_spectra")
         return torch.view_as_complex(out)
 
@@ -236,11 +314,12 @@ class Plan:
 class Job:
     """One queued filter call; fetch results, then release (or use as a context manager)."""
 
-    def __init__(self, plan: Plan, handle: ctypes.c_void_p, y):
+    def __init__(self, plan: Plan, handle: ctypes.c_void_p, y, lengths):
         self.plan = plan
         self._h = handle
         self._y = y  # the device input stays alive until the job is released
-        self.n_segments = y.shape[0]
+        self.lengths = list(lengths)
+        self.n_segments = len(self.lengths)
 
     def fetch_tails(self, capacity: int | None = None, allow_overflow: bool = False):
         """Tails sorted by (segment, template, lag) as a TAIL_DTYPE array, and the exact total."""
@@ -254,6 +333,12 @@ class Job:
         _check(st, "bfsearch_fetch_tails")
         return out[: nw.value], nt.value
 
+    def done(self) -> bool:
+        """True once every kernel of the job has finished (does not block)."""
+        d = ctypes.c_int()
+        _check(_lib.bfsearch_job_poll(self._h, ctypes.byref(d)), "bfsearch_job_poll")
+        return bool(d.value)
+
     def fetch_sigma(self) -> np.ndarray:
         out = np.zeros((self.n_segments, self.plan.k), dtype=np.float64)
         _check(_lib.bfsearch_fetch_sigma(self._h, ctypes.c_void_p(out.ctypes.data)), "bfsearch_fetch_sigma")
@@ -266,13 +351,17 @@ class Job:
         return c.value, t.value
 
     def spectra(self):
-        """Diagnostic: segment spectra Y_s[0..N/2] as complex128 [S, N/2 + 1]."""
+        """Diagnostic: segment spectra Y_s[0..N_s/2] as complex128; [S, N/2 + 1] when every
+        segment has the same length, else a list of 1-D tensors."""
         import torch
 
-        out = torch.empty((self.n_segments, self.plan.m + 1, 2), dtype=torch.float64,
-                          device=f"cuda:{self.plan.device}")
+        sizes = [n // 2 + 1 for n in self.lengths]
+        out = torch.empty((sum(sizes), 2), dtype=torch.float64, device=f"cuda:{self.plan.device}")
         _check(_lib.bfsearch_job_spectra(self._h, ctypes.c_void_p(out.data_ptr())), "bfsearch_job_spectra")
-        return torch.view_as_complex(out)
+        c = torch.view_as_complex(out)
+        if len(set(sizes)) == 1:
+            return c.view(len(sizes), sizes[0])
+        return list(torch.split(c, sizes))
 
     def release(self) -> None:
         if self._h:

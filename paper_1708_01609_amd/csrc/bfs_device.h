@@ -127,6 +127,60 @@ __device__ __forceinline__ cx<T> rot(cx<T> a) {
   }
 }
 
+template <typename T>
+__device__ __forceinline__ T fmad(T a, T b, T c) {
+  if constexpr (std::is_same_v<T, float>) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+
+// Radix-2 butterfly with a compile-time twiddle, fused-multiply-add form:
+//   x0 = e + w o,  x1 = e - w o,  w = exp(DIR 2 pi i K / R).
+// Trivial rotations cost 4 additions.  Otherwise the larger of cos and sin
+// is factored out (Linzer and Feig's FMA butterfly): with |c| >= |s|,
+// w o = c (o.x - t o.y, o.y + t o.x), t = s / c, so the pair costs 6 FMAs
+// instead of 4 multiply/FMAs plus 4 additions; odd eighths use 2 additions
+// and 4 FMAs with +-1/sqrt(2).
+template <int K, int R, int DIR, typename T>
+__device__ __forceinline__ void bfly(const cx<T>& e, const cx<T>& o, cx<T>& x0, cx<T>& x1) {
+  constexpr long k = ((long(K) % R) + R) % R;
+  if constexpr (k == 0 || 2 * k == R || 4 * k == R || 4 * k == 3 * R) {
+    const cx<T> t = rot<K, R, DIR>(o);
+    x0 = cadd(e, t);
+    x1 = csub(e, t);
+  } else if constexpr ((8 * k) % R == 0) {
+    constexpr T h = T(0.707106781186547524400844362104849039);
+    constexpr int oct = int(8 * k / R);
+    constexpr int sx = (oct == 1 || oct == 7) ? 1 : -1;
+    constexpr int sy0 = (oct == 1 || oct == 3) ? 1 : -1;
+    constexpr int sy = DIR > 0 ? sy0 : -sy0;
+    // w o = h (sx o.x - sy o.y, sy o.x + sx o.y)
+    T ux, uy;
+    if constexpr (sx > 0 && sy > 0) { ux = o.x - o.y; uy = o.x + o.y; }
+    else if constexpr (sx > 0 && sy < 0) { ux = o.x + o.y; uy = o.y - o.x; }
+    else if constexpr (sx < 0 && sy > 0) { ux = -o.x - o.y; uy = o.x - o.y; }
+    else { ux = o.y - o.x; uy = -o.x - o.y; }
+    x0 = {fmad<T>(h, ux, e.x), fmad<T>(h, uy, e.y)};
+    x1 = {fmad<T>(-h, ux, e.x), fmad<T>(-h, uy, e.y)};
+  } else {
+    constexpr double c = cs2pi(k, R, 0);
+    constexpr double s = DIR > 0 ? cs2pi(k, R, 1) : -cs2pi(k, R, 1);
+    constexpr bool cosf = (c < 0 ? -c : c) >= (s < 0 ? -s : s);
+    if constexpr (cosf) {
+      // w o = c (o.x - t o.y, o.y + t o.x)
+      constexpr T m = T(c), tq = T(s / c);
+      const T ux = fmad<T>(-tq, o.y, o.x), uy = fmad<T>(tq, o.x, o.y);
+      x0 = {fmad<T>(m, ux, e.x), fmad<T>(m, uy, e.y)};
+      x1 = {fmad<T>(-m, ux, e.x), fmad<T>(-m, uy, e.y)};
+    } else {
+      // w o = s (t o.x - o.y, t o.y + o.x), t = c / s
+      constexpr T m = T(s), tq = T(c / s);
+      const T ux = fmad<T>(tq, o.x, -o.y), uy = fmad<T>(tq, o.y, o.x);
+      x0 = {fmad<T>(m, ux, e.x), fmad<T>(m, uy, e.y)};
+      x1 = {fmad<T>(-m, ux, e.x), fmad<T>(-m, uy, e.y)};
+    }
+  }
+}
+
 // In-register DFT of size R on v[0..R) (natural order in and out):
 //   V[k] = sum_j v[j] exp(DIR * 2 pi i j k / R).
 // Recursive radix-2 decimation in time; every index and twiddle is a
@@ -157,9 +211,7 @@ __device__ __forceinline__ void dft(cx<T>* v) {
     dft<R / 2, DIR, T>(o);
     static_for<R / 2>([&](auto kc) {
       constexpr int k = decltype(kc)::value;
-      const cx<T> t = rot<k, R, DIR>(o[k]);
-      v[k] = cadd(e[k], t);
-      v[k + R / 2] = csub(e[k], t);
+      bfly<k, R, DIR, T>(e[k], o[k], v[k], v[k + R / 2]);
     });
   }
 }

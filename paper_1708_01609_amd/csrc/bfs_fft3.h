@@ -73,19 +73,29 @@ __device__ __forceinline__ void pin(cx<T>& a) {
 }
 __device__ __forceinline__ void pin(double& a) { asm volatile("" : "+v"(a)); }
 
-// Pass-1 column of slot c of thread t.  MIRROR places a column and its
-// Hermitian partner S1 - col in lanes l and l ^ 32 of the same wave (lane 32
-// of the first wave takes the self-paired column S1/2), so a thread's load of
-// its partner's spectrum hits the cache lines its neighbour lane just read.
-template <class F, bool MIRROR>
+// Pass-1 column of slot c of thread t.
+//  MAP_PLAIN        column = t + NT c.
+//  MAP_MIRROR       a column and its Hermitian partner S1 - col sit in lanes
+//                   l and l ^ 32 of one wave (lane 32 of the first wave takes
+//                   the self-paired column S1/2; column 0 pairs with itself).
+//  MAP_MIRROR_ODD   partners col and S1 - 1 - col in lanes l and l ^ 32 (the
+//                   pairing of the odd half of a split transform; no column
+//                   pairs with itself).
+enum ColMap : int { MAP_PLAIN = 0, MAP_MIRROR = 1, MAP_MIRROR_ODD = 2 };
+
+template <class F, int MAP>
 __device__ __forceinline__ uint32_t fft3_col(int t, int c) {
   const uint32_t tv = uint32_t(t + F::NT * c);
-  if constexpr (!MIRROR) {
+  if constexpr (MAP == MAP_PLAIN) {
     return tv;
   } else {
     const uint32_t w = tv >> 6, l = tv & 63u;
     const uint32_t lo = 32u * w + l;
-    const uint32_t hi = (tv == 32u) ? uint32_t(F::S1 / 2) : uint32_t(F::S1) - 32u * w - (l - 32u);
+    uint32_t hi;
+    if constexpr (MAP == MAP_MIRROR)
+      hi = (tv == 32u) ? uint32_t(F::S1 / 2) : uint32_t(F::S1) - 32u * w - (l - 32u);
+    else
+      hi = uint32_t(F::S1 - 1) - 32u * w - (l - 32u);
     return l < 32u ? lo : hi;
   }
 }

@@ -3,14 +3,21 @@
 //  fwd_fft_kernel   forward real FFT of one real series per workgroup (a
 //                   segment y, a grid chirp synthesised in place, or an
 //                   explicit template), as a complex FFT of length M = N/2 on
-//                   z_n = x_{2n} + i x_{2n+1}; writes the complex Z.
+//                   z_n = x_{2n} + i x_{2n+1}; writes the complex Z.  At
+//                   the split size (N = 2^17) a workgroup transforms the
+//                   even or the odd samples of z (length M/2) and the unpack
+//                   joins them.
 //  rfft_unpack_kernel   Z -> the half spectrum X_0..X_{N/2} in the packed
 //                   layout [M] (X_0 real in .x of slot 0, X_{N/2} real in .y),
-//                   scaled and converted to the storage type.
+//                   scaled and converted to the storage type.  Split rows
+//                   hold the even bins first, then the odd bins.
 //  corr_kernel      one correlation (segment s, template j) per workgroup:
 //                   C = conj(W) Y, FP64 Parseval sum, Hermitian repack,
 //                   inverse complex FFT of length M on chip, |rho| > kappa
 //                   sigma, ballot compaction of the tails.
+//  corr2_kernel     the same at the split size: the length-M inverse
+//                   transform runs as two length-M/2 transforms (even and
+//                   odd bins) joined by one radix-2 step.
 #pragma once
 
 #include "bfs_fft3.h"
@@ -37,38 +44,46 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
   return w;
 }
 
+// One forward transform per workgroup.  Segment items read their samples at
+// the device address seg_ptr[item]; explicit templates at src + item
+// src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
+// samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
+// The chirp source writes the FP64 sum of x^2 over the samples it made to
+// energy[b] (the unpack turns it into the unit-norm scale).
 template <typename T, class F, int SRC>
 __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
-    const void* __restrict__ src, uint64_t src_stride, uint32_t src_len,
+    const void* __restrict__ src, uint64_t src_stride, uint32_t src_len, const uint64_t* __restrict__ seg_ptr,
     const double* __restrict__ f0, const double* __restrict__ fdot, const uint32_t* __restrict__ len,
     double fs, int taper, uint32_t first,
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    cx<T>* __restrict__ out, double* __restrict__ inv_norm) {
+    cx<T>* __restrict__ out, double* __restrict__ energy, int split) {
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
   const uint32_t b = blockIdx.x;
+  const uint32_t item = split ? (b >> 1) : b;
+  const uint32_t half = split ? (b & 1u) : 0u;
+  const uint32_t cs = split ? 2u : 1u;  // stride of z between the transform's samples
   cx<T> v[F::P];
   double acc = 0.0;
   uint32_t cols[F::C1];
 #pragma unroll
-  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, false>(t, c);
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_PLAIN>(t, c);
 
-  // ---- load (source stage)
+  // ---- load (source stage): element (col, k2) is z_kk, kk = cs (col + S1 k2) + half
   if constexpr (SRC == SRC_CHIRP) {
-    const uint32_t j = first + b;
+    const uint32_t j = first + item;
     const double pf0 = f0[j], pfd = fdot[j];
     const int L = int(len[j]);
 #pragma unroll
     for (int c = 0; c < F::C1; ++c) {
-      const int col = int(cols[c]);
 #pragma unroll
       for (int k2 = 0; k2 < F::R1; ++k2) {
-        const int k = col + F::S1 * k2;
+        const int kk = int(cs * (cols[c] + uint32_t(F::S1 * k2)) + half);
         double a = 0.0, bb = 0.0;
-        if (2 * k < L) {
-          a = chirp_sample(2 * k, L, pf0, pfd, fs, taper);
-          bb = chirp_sample(2 * k + 1, L, pf0, pfd, fs, taper);
+        if (2 * kk < L) {
+          a = chirp_sample(2 * kk, L, pf0, pfd, fs, taper);
+          bb = chirp_sample(2 * kk + 1, L, pf0, pfd, fs, taper);
         }
         acc += a * a + bb * bb;
         v[c * F::R1 + k2] = {T(a), T(bb)};
@@ -80,26 +95,26 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
       }
     }
   } else if constexpr (SRC == SRC_EXPLICIT) {
-    const double* x = static_cast<const double*>(src) + uint64_t(first + b) * src_stride;
+    const double* x = static_cast<const double*>(src) + uint64_t(first + item) * src_stride;
 #pragma unroll
     for (int c = 0; c < F::C1; ++c) {
-      const int col = int(cols[c]);
 #pragma unroll
       for (int k2 = 0; k2 < F::R1; ++k2) {
-        const int k = col + F::S1 * k2;
-        const double a = (uint32_t(2 * k) < src_len) ? x[2 * k] : 0.0;
-        const double bb = (uint32_t(2 * k + 1) < src_len) ? x[2 * k + 1] : 0.0;
+        const uint32_t kk = cs * (cols[c] + uint32_t(F::S1 * k2)) + half;
+        const double a = (2 * kk < src_len) ? x[2 * kk] : 0.0;
+        const double bb = (2 * kk + 1 < src_len) ? x[2 * kk + 1] : 0.0;
         v[c * F::R1 + k2] = {T(a), T(bb)};
       }
     }
   } else {
-    const T* x = static_cast<const T*>(src) + uint64_t(b) * src_stride;
-    const rsrc_t rx = make_rsrc(x, uint32_t(F::M) * uint32_t(sizeof(cx<T>)));
+    const T* x = reinterpret_cast<const T*>(uintptr_t(seg_ptr[item]));
+    constexpr uint32_t SC = sizeof(cx<T>);
+    const rsrc_t rx = make_rsrc(x, cs * uint32_t(F::M) * SC);
 #pragma unroll
     for (int c = 0; c < F::C1; ++c) {
 #pragma unroll
       for (int k2 = 0; k2 < F::R1; ++k2)
-        v[c * F::R1 + k2] = buf_load<cx<T>>(rx, cols[c] * uint32_t(sizeof(cx<T>)), uint32_t(F::S1 * k2) * uint32_t(sizeof(cx<T>)));
+        v[c * F::R1 + k2] = buf_load<cx<T>>(rx, (cs * cols[c] + half) * SC, cs * uint32_t(F::S1 * k2) * SC);
     }
   }
 
@@ -119,7 +134,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     if (t == 0) {
       double s = 0.0;
       for (int w = 0; w < F::NW; ++w) s += red[w];
-      inv_norm[b] = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+      energy[b] = s;
     }
   }
   __syncthreads();
@@ -137,46 +152,68 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
   }
 }
 
+// Position of bin k (0 < k < M) in a stored row: k itself, or for split rows
+// k/2 for even k and M/2 + (k-1)/2 for odd k.  Slot 0 holds X_0 and X_M.
+__device__ __forceinline__ uint32_t bin_pos(uint32_t k, uint32_t M, int split) {
+  return split ? ((k & 1u) ? (M >> 1) + (k >> 1) : (k >> 1)) : k;
+}
+
 // Z (complex FFT of z_n = x_{2n} + i x_{2n+1}) -> packed half spectrum of x:
 //   E_k = (Z_k + conj Z_{M-k}) / 2,  O_k = -i (Z_k - conj Z_{M-k}) / 2,
 //   X_k = E_k + exp(-2 pi i k / N) O_k,   X_{M-k} = conj(E_k - exp(-2 pi i k/N) O_k),
 //   X_0 = Re Z_0 + Im Z_0,  X_M = Re Z_0 - Im Z_0 (both real).
-// tw_u holds exp(+2 pi i k / N); scale (per row, may be null) multiplies X.
-// Z and out may alias (in-place): each thread reads both of its slots first.
+// tw_u holds exp(+2 pi i k / N), k < M.  A split item holds the transforms A
+// (even samples) and B (odd samples) of length H = M/2, and
+//   Z_k = A_{k mod H} + exp(-2 pi i k / M) B_{k mod H},  exp(2 pi i r / M) = tw_u[2 r].
+// energy (may be null): per transform the sum of x^2; the scale is
+// 1 / sqrt(total) (two partial sums per split item).
+// Z and out may alias when not split (in place): each thread reads both of
+// its slots before writing them.
 template <typename T, typename TW>
-__global__ __launch_bounds__(256) void rfft_unpack_kernel(const cx<T>* Z, TW* out,
-                                                          const double* __restrict__ scale,
+__global__ __launch_bounds__(256) void rfft_unpack_kernel(const cx<T>* Z, TW* out, const double* __restrict__ energy,
                                                           const cx<T>* __restrict__ tw_u, uint32_t M,
-                                                          uint64_t out_row_offset) {
+                                                          uint64_t out_row_offset, int split) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t b = blockIdx.y;
   if (k > M / 2) return;
   const cx<T>* z = Z + uint64_t(b) * M;
   TW* o = out + (out_row_offset + b) * uint64_t(M);
-  const T sc = scale ? T(scale[b]) : T(1);
+  T sc = T(1);
+  if (energy) {
+    const double e = split ? energy[2 * b] + energy[2 * b + 1] : energy[b];
+    sc = e > 0.0 ? T(1.0 / sqrt(e)) : T(0);
+  }
+  const uint32_t H = M >> 1;
+  auto zat = [&](uint32_t kk) -> cx<T> {  // Z_kk, kk < M
+    if (!split) return z[kk];
+    const uint32_t r = kk < H ? kk : kk - H;
+    cx<T> w = conjg(tw_u[2 * r]);
+    if (kk >= H) w = {-w.x, -w.y};
+    return cadd(z[r], cmul(w, z[H + r]));
+  };
   if (k == 0) {
-    const cx<T> z0 = z[0];
+    const cx<T> z0 = zat(0);
     store_spec<TW, T>(o, 0, cx<T>{(z0.x + z0.y) * sc, (z0.x - z0.y) * sc});
     return;
   }
-  const cx<T> zk = z[k], zp = z[M - k];
+  const cx<T> zk = zat(k), zp = zat(M - k);
   const cx<T> e = {T(0.5) * (zk.x + zp.x), T(0.5) * (zk.y - zp.y)};
   // O = -i/2 (Zk - conj Zp) = 1/2 (Im(Zk) + Im(Zp), -(Re Zk - Re Zp))
   const cx<T> od = {T(0.5) * (zk.y + zp.y), T(-0.5) * (zk.x - zp.x)};
   const cx<T> w = conjg(tw_u[k]);
   const cx<T> wo = cmul(w, od);
   const cx<T> xk = {(e.x + wo.x) * sc, (e.y + wo.y) * sc};
-  store_spec<TW, T>(o, k, xk);
+  store_spec<TW, T>(o, bin_pos(k, M, split), xk);
   if (M - k != k) {
     const cx<T> xp = {(e.x - wo.x) * sc, -(e.y - wo.y) * sc};
-    store_spec<TW, T>(o, M - k, xp);
+    store_spec<TW, T>(o, bin_pos(M - k, M, split), xp);
   }
 }
 
-// Packed storage -> FP64 interleaved [rows][M+1][2] (diagnostics).
+// Packed storage -> FP64 interleaved [rows][M+1][2] in natural bin order (diagnostics).
 template <typename T, typename TW>
 __global__ __launch_bounds__(256) void spectrum_export_kernel(const TW* __restrict__ in, double* __restrict__ out,
-                                                              uint32_t M, uint64_t first_row) {
+                                                              uint32_t M, uint64_t first_row, int split) {
   const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t b = blockIdx.y;
   if (k > M) return;
@@ -190,7 +227,7 @@ __global__ __launch_bounds__(256) void spectrum_export_kernel(const TW* __restri
     re = double(load_spec<TW, T>(row, 0).y);
     im = 0.0;
   } else {
-    const cx<T> a = load_spec<TW, T>(row, k);
+    const cx<T> a = load_spec<TW, T>(row, bin_pos(k, M, split));
     re = double(a.x);
     im = double(a.y);
   }
@@ -204,56 +241,44 @@ __global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long
 }
 
 // ------------------------------------------------------------ correlation --
-// One workgroup per (template j = blockIdx.x, segment s = blockIdx.y).
-//   bank  [K][M] packed template spectra (storage TW), Y [S][M] packed.
-//   tw_u  exp(+2 pi i k / N), tw1/tw2 the FFT twiddles (see bfs_fft3.h).
-// Repack of the Hermitian product C for the length-M inverse transform:
-//   Z_k = (C_k + conj C_{M-k}) + i exp(+2 pi i k / N) (C_k - conj C_{M-k}),
-// then z = IDFT_M(Z) gives z_n = N (rho_{2n} + i rho_{2n+1}).
-// Parseval (FP64): S = |C_0|^2 + |C_M|^2 + 2 sum_{k=1}^{M-1} |C_k|^2,
-// sigma = sqrt(S) / N and |rho| > kappa sigma  <=>  |z| > kappa sqrt(S).
-template <typename T, typename TW, class F, bool DENSE>
-__global__ __launch_bounds__(F::NT) void corr_kernel(
-    const TW* __restrict__ bank, const cx<T>* __restrict__ yspec,
-    const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    uint32_t K, double kappa, double* __restrict__ sigma_out,
-    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
-    T* __restrict__ rho_dense) {
-  constexpr int M = F::M;
-  constexpr double N = 2.0 * M;
-  __shared__ T lds[F::LDS_ELEMS];
-  __shared__ double red[F::NW];
-  const int t = threadIdx.x;
-  const uint32_t j = blockIdx.x, s = blockIdx.y;
-  const TW* W = bank + uint64_t(j) * M;
-  const cx<T>* Y = yspec + uint64_t(s) * M;
-  const rsrc_t rW = make_rsrc(W, uint32_t(M) * uint32_t(sizeof(TW)));
-  const rsrc_t rY = make_rsrc(Y, uint32_t(M) * uint32_t(sizeof(cx<T>)));
-  cx<T> v[F::P];
-  double acc = 0.0;
-
-  // ---- spectral product and Parseval partial sum.  Element (col, k2) is
-  // k = col + S1 k2; slot 0 of thread 0 packs the real C_0 (x) and C_M (y).
-  // The loads run one group of G elements ahead of the arithmetic.
-  constexpr int G = 2, NG = F::R1 / G;
-  static_assert(F::R1 % G == 0 && F::R1 % 2 == 0, "group size");
+// Stage 1: spectral product, Parseval partial sum and Hermitian repack of one
+// block of F::M bins, read from element row_off of the rows: the whole half
+// spectrum (MAP_MIRROR, row_off 0), or at the split size the even bins
+// (MAP_MIRROR, row_off 0) or the odd bins (MAP_MIRROR_ODD, row_off F::M).
+//   C_k = conj(W_k) Y_k;  acc += 2 |C_k|^2 in FP64, and |C_0|^2 + |C_M|^2 for slot 0;
+//   Z_k = (C_k + conj C_{M-k}) + i exp(+2 pi i k / N) (C_k - conj C_{M-k}).
+// Element (col, k2) of the block is bin index k' = col + S1 k2.  Its partner
+// (bin M-k) is held by lane l ^ 32 of the same wave at register R1-1-k2 under
+// both mirror maps, so registers k2 and R1-1-k2 swap halves as a pair.  Under
+// MAP_MIRROR columns 0 and S1/2 (lanes 0 and 32 of wave 0) pair inside their
+// own column: col 0 with index (R1 - k2) mod R1 (k2 = 0 with C_M, packed in
+// slot 0), col S1/2 with R1-1-k2; the odd map has no self-paired column.
+// exp(2 pi i k / N) = tw_u[bu_mul col + bu_add] exp(i pi k2 / R1) (bin
+// k = bu_mul k' + bu_add): one table load per column, a constant rotation per
+// element.
+template <class F, int MAP, int G, typename T, typename TW>
+__device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* cols, const rsrc_t& rW,
+                                         const rsrc_t& rY, uint32_t row_off, const cx<T>* __restrict__ tw_u,
+                                         uint32_t bu_mul, uint32_t bu_add, int t) {
+  // The loads run one group of G elements ahead of the arithmetic (the
+  // autotuner picks G; deeper groups hide more latency, cost registers).
+  constexpr int NG = F::R1 / G;
+  static_assert(G >= 1 && F::R1 % G == 0 && F::R1 % 2 == 0, "group size");
   constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
-  uint32_t cols[F::C1];
-#pragma unroll
-  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, true>(t, c);
+  constexpr bool HAS_DC = MAP == MAP_MIRROR;
   T cM = T(0);  // C_M of thread 0 (real)
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
     const uint32_t col = cols[c];
-    const bool dc = (c == 0) && (col == 0u);
+    const bool dc = HAS_DC && (c == 0) && (col == 0u);
     TW lw[2][G];
     cx<T> ly[2][G];
     auto issue = [&](int g, int buf) {
 #pragma unroll
       for (int e = 0; e < G; ++e) {
         const uint32_t k2 = uint32_t(g * G + e);
-        lw[buf][e] = buf_load<TW>(rW, col * SW, uint32_t(F::S1) * k2 * SW);
-        ly[buf][e] = buf_load<cx<T>>(rY, col * SY, uint32_t(F::S1) * k2 * SY);
+        lw[buf][e] = buf_load<TW>(rW, col * SW, (row_off + uint32_t(F::S1) * k2) * SW);
+        ly[buf][e] = buf_load<cx<T>>(rY, col * SY, (row_off + uint32_t(F::S1) * k2) * SY);
       }
     };
     issue(0, 0);
@@ -264,14 +289,14 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
         constexpr int e = decltype(ec)::value;
         constexpr int k2 = g * G + e;
         cx<T> wk = load_spec<TW, T>(&lw[g & 1][e], 0), yk = ly[g & 1][e];
-        if constexpr (k2 == 0) {
+        if constexpr (HAS_DC && k2 == 0) {
           if (c == 0) cM = dc ? wk.y * yk.y : T(0);
           wk.y = dc ? T(0) : wk.y;
           yk.y = dc ? T(0) : yk.y;
         }
         const cx<T> ck = cmulc(wk, yk);
         double pk = 2.0 * (double(ck.x) * double(ck.x) + double(ck.y) * double(ck.y));
-        if constexpr (k2 == 0) {
+        if constexpr (HAS_DC && k2 == 0) {
           const double pdc = double(ck.x) * double(ck.x) + double(cM) * double(cM);
           pk = dc ? pdc : pk;
         }
@@ -284,19 +309,11 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     });
   }
 
-  // ---- Hermitian repack for the length-M inverse transform:
-  //   Z_k = (C_k + conj C_{M-k}) + i exp(+2 pi i k / N) (C_k - conj C_{M-k}).
-  // The partner of (col, k2) is (S1 - col, R1-1-k2), held by lane l ^ 32 of the
-  // same wave at register R1-1-k2 (mirror column map), so registers k2 and
-  // R1-1-k2 swap halves as a pair.  Columns 0 and S1/2 (lanes 0 and 32 of
-  // wave 0) pair inside their own column: col 0 with index (R1 - k2) mod R1
-  // (k2 = 0 with C_M), col S1/2 with R1-1-k2.  exp(2 pi i k / N) =
-  // exp(2 pi i col / N) exp(i pi k2 / R1): one table load per column.
   const int lane = t & 63;
   const bool wave0 = t < 64;
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
-    const cx<T> bu = tw_u[cols[c]];
+    const cx<T> bu = tw_u[bu_mul * cols[c] + bu_add];
     cx<T> carry = {T(0), T(0)};
     static_for<F::R1 / 2>([&](auto kc) {
       constexpr int r1 = decltype(kc)::value;
@@ -304,14 +321,16 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
       const cx<T> A = v[c * F::R1 + r1], B = v[c * F::R1 + r2];
       cx<T> PA, PB;
       partner_pair(A, B, PA, PB);
-      if (c == 0 && wave0) {
-        const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
-        const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
-        PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
-        PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
-        PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
-        PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
-        carry = B;
+      if constexpr (HAS_DC) {
+        if (c == 0 && wave0) {
+          const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
+          const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
+          PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
+          PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
+          PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
+          PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
+          carry = B;
+        }
       }
       auto repack = [&](const cx<T>& ck, const cx<T>& cp, const cx<T>& tk) {
         const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
@@ -327,7 +346,14 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     });
     sched_fence();
   }
+}
 
+// Stage 2: inverse transform of length F::M on chip.  Returns the workgroup
+// sum of every thread's acc, reduced in a fixed order (deterministic).
+template <class F, typename T>
+__device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const uint32_t* cols,
+                                            const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2, int t,
+                                            double acc) {
   fft3_pass1<F, +1>(v, tw1, cols);
   {
     const double ws = wave_sum(acc);
@@ -347,62 +373,189 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   fft3_pass2<F, +1>(v, tw2, t);
   fft3_ex2<F>(v, lds, t);
   fft3_pass3<F, +1>(v);
+  return S;
+}
 
+// Stage 3, dense: z(i) is the value of register i (= N (rho_{2n} + i
+// rho_{2n+1}) at n = n_off + output index of i); rho goes into the row.
+template <class F, typename T, class Z>
+__device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, const rsrc_t& rrow, int t) {
+  const T inv = T(1.0 / N);
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) {
+    const uint32_t n0m0 = uint32_t(fft3_out_index<F>(t, c, 0)) + n_off;
+#pragma unroll
+    for (int mp = 0; mp < F::R3; ++mp) {
+      const cx<T> a = z(c * F::R3 + mp);
+      buf_store(cx<T>{a.x * inv, a.y * inv}, rrow, n0m0 * uint32_t(sizeof(cx<T>)),
+                uint32_t(F::R1 * F::R2 * mp) * uint32_t(sizeof(cx<T>)));
+    }
+  }
+}
+
+// Stage 3, threshold: keep |z| > thr (thr = kappa sqrt(S) in z units) with
+// one ballot per value and one atomicAdd per wave and value; records past
+// cap are counted but not written.  any: this thread may hold a tail.
+template <class F, typename T, class Z>
+__device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool any, uint32_t s, uint32_t j,
+                                           double N, tail_rec* __restrict__ tails,
+                                           unsigned long long* __restrict__ counter, uint64_t cap, int t) {
+  const int lane = t & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) {
+#pragma unroll
+    for (int mp = 0; mp < F::R3; ++mp) {
+      const uint32_t n = uint32_t(fft3_out_index<F>(t, c, mp)) + n_off;
+      const cx<T> a = z(c * F::R3 + mp);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const T val = h ? a.y : a.x;
+        const bool pred = any && (fabs(val) > thr);
+        const uint64_t mask = __ballot(pred);
+        if (mask) {
+          const int leader = __ffsll((unsigned long long)mask) - 1;
+          unsigned long long base = 0;
+          if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+          base = __shfl(base, leader, 64);
+          if (pred) {
+            const uint64_t idx = base + __popcll(mask & below);
+            if (idx < cap) {
+              tail_rec r;
+              r.segment = s;
+              r.template_id = j;
+              r.lag = 2 * n + uint32_t(h);
+              r.reserved = 0;
+              r.rho = double(val) / N;
+              tails[idx] = r;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// One workgroup per (template j = blockIdx.x, spectrum row blockIdx.y).
+//   bank  [K][M] packed template spectra (storage TW), yspec [rows][M] packed;
+//   row r is segment seg_ids[r] (or r), the id used for sigma and tails.
+//   tw_u  exp(+2 pi i k / N), tw1/tw2 the FFT twiddles (see bfs_fft3.h).
+// z = IDFT_M(Z) gives z_n = N (rho_{2n} + i rho_{2n+1}); with
+// S = |C_0|^2 + |C_M|^2 + 2 sum_{k=1}^{M-1} |C_k|^2 (FP64), sigma = sqrt(S)/N and
+// |rho| > kappa sigma  <=>  |z| > kappa sqrt(S).
+template <typename T, typename TW, class F, bool DENSE, int G>
+__global__ __launch_bounds__(F::NT) void corr_kernel(
+    const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
+    const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
+    uint32_t K, double kappa, double* __restrict__ sigma_out,
+    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    T* __restrict__ rho_dense) {
+  constexpr int M = F::M;
+  constexpr double N = 2.0 * M;
+  __shared__ T lds[F::LDS_ELEMS];
+  __shared__ double red[F::NW];
+  const int t = threadIdx.x;
+  const uint32_t j = blockIdx.x, row = blockIdx.y;
+  const uint32_t s = seg_ids ? seg_ids[row] : row;
+  const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
+  const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
+  cx<T> v[F::P];
+  double acc = 0.0;
+  uint32_t cols[F::C1];
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
+  corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
+  const double S = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
-
+  auto z = [&](int i) { return v[i]; };
   if constexpr (DENSE) {
     const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * K + j) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
-    const T inv = T(1.0 / N);
-#pragma unroll
-    for (int c = 0; c < F::C2; ++c) {
-      const uint32_t n0m0 = uint32_t(fft3_out_index<F>(t, c, 0));
-#pragma unroll
-      for (int mp = 0; mp < F::R3; ++mp)
-        buf_store(cx<T>{v[c * F::R3 + mp].x * inv, v[c * F::R3 + mp].y * inv}, rr, n0m0 * uint32_t(sizeof(cx<T>)),
-                  uint32_t(F::R1 * F::R2 * mp) * uint32_t(sizeof(cx<T>)));
-    }
+    emit_dense<F, T>(z, 0u, N, rr, t);
   } else {
-    // ---- threshold and compaction
     const T thr = T(kappa * rootS);
     T mx = T(0);
 #pragma unroll
     for (int i = 0; i < F::P; ++i) mx = fmax(mx, fmax(fabs(v[i].x), fabs(v[i].y)));
     const bool any = (mx > thr) && (rootS > 0.0);
+    if (__ballot(any)) emit_tails<F, T>(z, 0u, thr, any, s, j, N, tails, counter, cap, t);
+  }
+}
+
+// Split size: M = 2 H, H = F::M.  The even bins (row elements [0, H)) and
+// the odd bins ([H, M)) are each repacked and inverse-transformed at length
+// H, giving E and O; then
+//   z_n = E_n + exp(2 pi i n / M) O_n,   z_{n+H} = E_n - exp(2 pi i n / M) O_n.
+// E waits in per-thread scratch memory while the odd half runs (each thread
+// reads back only what it stored).  exp(2 pi i n / M) for
+// n = n0 + R1 m0 + R1 R2 m' is tw_u[2 (n0 + R1 m0)] exp(i pi m' / R3).
+template <typename T, typename TW, class F, bool DENSE, int G>
+__global__ __launch_bounds__(F::NT) void corr2_kernel(
+    const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
+    const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
+    uint32_t K, double kappa, double* __restrict__ sigma_out,
+    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    T* __restrict__ rho_dense) {
+  constexpr int H = F::M, M = 2 * H;
+  constexpr double N = 2.0 * M;
+  __shared__ T lds[F::LDS_ELEMS];
+  __shared__ double red[F::NW];
+  const int t = threadIdx.x;
+  const uint32_t j = blockIdx.x, row = blockIdx.y;
+  const uint32_t s = seg_ids ? seg_ids[row] : row;
+  const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
+  const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
+  cx<T> v[F::P];
+  volatile T ex[F::P], ey[F::P];  // E, kept in scratch memory
+
+  double acc = 0.0;
+  uint32_t cols[F::C1];
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
+  corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 2u, 0u, t);
+  const double S0 = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
+#pragma unroll
+  for (int i = 0; i < F::P; ++i) {
+    ex[i] = v[i].x;
+    ey[i] = v[i].y;
+  }
+  __syncthreads();  // every wave is done with the even half's LDS before the odd half writes it
+
+  acc = 0.0;
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR_ODD>(t, c);
+  corr_pre<F, MAP_MIRROR_ODD, G, T, TW>(v, acc, cols, rW, rY, uint32_t(H), tw_u, 2u, 1u, t);
+  const double S = S0 + corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
+  const double rootS = sqrt(S);
+  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
+
+  // v <- exp(2 pi i n / M) O_n
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) {
+    const cx<T> bc = tw_u[2 * fft3_out_index<F>(t, c, 0)];
+    static_for<F::R3>([&](auto mc) {
+      constexpr int mp = decltype(mc)::value;
+      v[c * F::R3 + mp] = cmul(rot<mp, 2 * F::R3, +1>(bc), v[c * F::R3 + mp]);
+    });
+  }
+  auto z_lo = [&](int i) { return cx<T>{ex[i] + v[i].x, ey[i] + v[i].y}; };
+  auto z_hi = [&](int i) { return cx<T>{ex[i] - v[i].x, ey[i] - v[i].y}; };
+  if constexpr (DENSE) {
+    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * K + j) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
+    emit_dense<F, T>(z_lo, 0u, N, rr, t);
+    emit_dense<F, T>(z_hi, uint32_t(H), N, rr, t);
+  } else {
+    const T thr = T(kappa * rootS);
+    T mx = T(0);
+#pragma unroll
+    for (int i = 0; i < F::P; ++i) {
+      const T a = ex[i], b = ey[i];
+      mx = fmax(mx, fmax(fmax(fabs(a + v[i].x), fabs(b + v[i].y)), fmax(fabs(a - v[i].x), fabs(b - v[i].y))));
+    }
+    const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
-      const int lane = t & 63;
-      const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-      for (int c = 0; c < F::C2; ++c) {
-#pragma unroll
-        for (int mp = 0; mp < F::R3; ++mp) {
-          const int n = fft3_out_index<F>(t, c, mp);
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const T val = h ? v[c * F::R3 + mp].y : v[c * F::R3 + mp].x;
-            const bool pred = any && (fabs(val) > thr);
-            const uint64_t mask = __ballot(pred);
-            if (mask) {
-              const int leader = __ffsll((unsigned long long)mask) - 1;
-              unsigned long long base = 0;
-              if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-              base = __shfl(base, leader, 64);
-              if (pred) {
-                const uint64_t idx = base + __popcll(mask & below);
-                if (idx < cap) {
-                  tail_rec r;
-                  r.segment = s;
-                  r.template_id = j;
-                  r.lag = uint32_t(2 * n + h);
-                  r.reserved = 0;
-                  r.rho = double(val) / N;
-                  tails[idx] = r;
-                }
-              }
-            }
-          }
-        }
-      }
+      emit_tails<F, T>(z_lo, 0u, thr, any, s, j, N, tails, counter, cap, t);
+      emit_tails<F, T>(z_hi, uint32_t(H), thr, any, s, j, N, tails, counter, cap, t);
     }
   }
 }

@@ -1,10 +1,11 @@
 // C ABI and host runtime of the matched-filter library (see include/bfsearch.h).
 //
-// A plan owns the resident template bank (spectra of every template, built
-// on the device at plan time) and the FFT twiddle tables.  A job owns the
-// per-call buffers (segment spectra, sigma, tail buffer, tail counter) which
-// return to a per-plan pool on release, so steady-state filter calls do not
-// allocate.
+// A plan owns, for every segment length it accepts (the powers of two in
+// [n_min, n]), the resident template bank at that length (the spectra of
+// every template zero-padded to it, built on the device at plan time) and the
+// FFT twiddle tables.  A job owns the per-call buffers (segment spectra,
+// sigma, tail buffer and counter, segment table) which return to a per-plan
+// pool on release, so steady-state filter calls do not allocate.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
@@ -23,26 +24,17 @@ static_assert(sizeof(tail_rec) == sizeof(bfs_tail), "tail record layout");
 namespace {
 
 // ---------------------------------------------------------------- kernels --
-// Kernel configuration per (real type, M = N/2): radices R1*R2*R3 = M and
-// threads per workgroup.
-template <typename T, int M>
-struct CfgFor;
-template <> struct CfgFor<float, 512> { using F = Fft3<float, 8, 8, 8, 64>; };
-template <> struct CfgFor<float, 1024> { using F = Fft3<float, 4, 16, 16, 64>; };
-template <> struct CfgFor<float, 2048> { using F = Fft3<float, 8, 16, 16, 128>; };
-template <> struct CfgFor<float, 4096> { using F = Fft3<float, 16, 16, 16, 256>; };
-template <> struct CfgFor<float, 8192> { using F = Fft3<float, 8, 32, 32, 256>; };
-template <> struct CfgFor<float, 16384> { using F = Fft3<float, 16, 32, 32, 512>; };
-template <> struct CfgFor<float, 32768> { using F = Fft3<float, 32, 32, 32, 1024>; };
-template <> struct CfgFor<double, 512> { using F = Fft3<double, 8, 8, 8, 64>; };
-template <> struct CfgFor<double, 1024> { using F = Fft3<double, 4, 16, 16, 64>; };
-template <> struct CfgFor<double, 2048> { using F = Fft3<double, 8, 16, 16, 128>; };
-template <> struct CfgFor<double, 4096> { using F = Fft3<double, 16, 16, 16, 256>; };
-
+// A kernel configuration per (real type, storage type, M = N/2): radices
+// R1*R2*R3 and threads per workgroup of the on-chip transform, whether the
+// length-M inverse transform runs as two halves (split, when M points do not
+// fit one workgroup's registers), and the load-group depth G of the product
+// stage.  Each M has a short list of candidates; the first is the default and
+// the autotuner may pick another by timing (see tune_size).
 struct FwdArgs {
-  const void* src;
+  const void* src;          // explicit templates [K][src_stride] (FP64)
   uint64_t src_stride;
   uint32_t src_len;
+  const uint64_t* seg_ptr;  // segment sources: device address of each item's samples
   const double* f0;
   const double* fdot;
   const uint32_t* len;
@@ -52,12 +44,13 @@ struct FwdArgs {
   const void* tw1;
   const void* tw2;
   void* out;
-  double* inv_norm;
+  double* energy;
 };
 
 struct CorrArgs {
   const void* bank;
   const void* y;
+  const uint32_t* seg_ids;  // global segment id of each grid row (null: the row index)
   const void* tw_u;
   const void* tw1;
   const void* tw2;
@@ -71,112 +64,180 @@ struct CorrArgs {
 };
 
 struct KernelSet {
-  int R1, R2, R3, NT, M;
+  int R1, R2, R3, NT;
+  int FM;            // length of the on-chip transform
+  int M;             // N/2 (= FM, or 2 FM when split)
+  int split;
+  int G;             // load-group depth of the product stage
   size_t real_size;  // sizeof(T)
   size_t spec_size;  // bytes of one stored template spectrum element
   hipError_t (*fwd)(int src, uint32_t batch, hipStream_t st, const FwdArgs& a);
-  hipError_t (*unpack_bank)(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* scale,
+  hipError_t (*unpack_bank)(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
                             const void* tw_u, uint64_t row_off);
-  hipError_t (*unpack_y)(uint32_t batch, hipStream_t st, void* Z, const void* tw_u);
+  hipError_t (*unpack_y)(uint32_t batch, hipStream_t st, const void* Z, void* out, const void* tw_u);
   hipError_t (*corr)(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a);
   hipError_t (*export_bank)(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first);
   hipError_t (*export_y)(uint32_t count, hipStream_t st, const void* y, double* out);
 };
 
-template <typename T, typename TW, class F>
+template <typename T, typename TW, class F, int SPLIT, int G>
 struct Impl {
+  static constexpr int M = F::M * (SPLIT ? 2 : 1);
   static hipError_t fwd(int src, uint32_t batch, hipStream_t st, const FwdArgs& a) {
-    const dim3 grid(batch), block(F::NT);
+    const dim3 grid(batch * (SPLIT ? 2u : 1u)), block(F::NT);
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
     auto* out = static_cast<cx<T>*>(a.out);
     if (src == SRC_SAMPLES)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.inv_norm);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     else if (src == SRC_CHIRP)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.inv_norm);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     else
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.inv_norm);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     return hipGetLastError();
   }
-  static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* scale,
+  static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
                                 const void* tw_u, uint64_t row_off) {
-    const dim3 grid((F::M / 2 + 1 + 255) / 256, batch);
+    const dim3 grid((M / 2 + 1 + 255) / 256, batch);
     hipLaunchKernelGGL((rfft_unpack_kernel<T, TW>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(Z),
-                       static_cast<TW*>(out), scale, static_cast<const cx<T>*>(tw_u), uint32_t(F::M), row_off);
+                       static_cast<TW*>(out), energy, static_cast<const cx<T>*>(tw_u), uint32_t(M), row_off, SPLIT);
     return hipGetLastError();
   }
-  static hipError_t unpack_y(uint32_t batch, hipStream_t st, void* Z, const void* tw_u) {
-    const dim3 grid((F::M / 2 + 1 + 255) / 256, batch);
+  static hipError_t unpack_y(uint32_t batch, hipStream_t st, const void* Z, void* out, const void* tw_u) {
+    const dim3 grid((M / 2 + 1 + 255) / 256, batch);
     hipLaunchKernelGGL((rfft_unpack_kernel<T, cx<T>>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(Z),
-                       static_cast<cx<T>*>(Z), static_cast<const double*>(nullptr),
-                       static_cast<const cx<T>*>(tw_u), uint32_t(F::M), uint64_t(0));
+                       static_cast<cx<T>*>(out), static_cast<const double*>(nullptr),
+                       static_cast<const cx<T>*>(tw_u), uint32_t(M), uint64_t(0), SPLIT);
     return hipGetLastError();
   }
-  static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    const dim3 grid(a.K, S), block(F::NT);
+  template <bool DENSE>
+  static void launch_corr(dim3 grid, hipStream_t st, const CorrArgs& a) {
     const auto* bank = static_cast<const TW*>(a.bank);
     const auto* y = static_cast<const cx<T>*>(a.y);
     const auto* tu = static_cast<const cx<T>*>(a.tw_u);
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
-    if (dense)
-      hipLaunchKernelGGL((corr_kernel<T, TW, F, true>), grid, block, 0, st, bank, y, tu, t1, t2, a.K, a.kappa,
-                         a.sigma, a.tails, a.counter, a.cap, static_cast<T*>(a.rho));
+    T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
+    if constexpr (SPLIT)
+      hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
+                         a.K, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
     else
-      hipLaunchKernelGGL((corr_kernel<T, TW, F, false>), grid, block, 0, st, bank, y, tu, t1, t2, a.K, a.kappa,
-                         a.sigma, a.tails, a.counter, a.cap, static_cast<T*>(nullptr));
+      hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
+                         a.K, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
+  }
+  static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
+    const dim3 grid(a.K, S);
+    if (dense)
+      launch_corr<true>(grid, st, a);
+    else
+      launch_corr<false>(grid, st, a);
     return hipGetLastError();
   }
   static hipError_t export_bank(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first) {
-    const dim3 grid((F::M + 1 + 255) / 256, count);
+    const dim3 grid((M + 1 + 255) / 256, count);
     hipLaunchKernelGGL((spectrum_export_kernel<T, TW>), grid, dim3(256), 0, st, static_cast<const TW*>(bank), out,
-                       uint32_t(F::M), first);
+                       uint32_t(M), first, SPLIT);
     return hipGetLastError();
   }
   static hipError_t export_y(uint32_t count, hipStream_t st, const void* y, double* out) {
-    const dim3 grid((F::M + 1 + 255) / 256, count);
+    const dim3 grid((M + 1 + 255) / 256, count);
     hipLaunchKernelGGL((spectrum_export_kernel<T, cx<T>>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(y),
-                       out, uint32_t(F::M), uint64_t(0));
+                       out, uint32_t(M), uint64_t(0), SPLIT);
     return hipGetLastError();
   }
   static const KernelSet* get() {
-    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, sizeof(T), sizeof(TW),
+    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW),
                                  &fwd, &unpack_bank, &unpack_y, &corr, &export_bank, &export_y};
     return &ks;
   }
 };
 
+constexpr int MAX_CANDIDATES = 8;
+
+struct Candidates {
+  const KernelSet* ks[MAX_CANDIDATES];
+  int count = 0;
+  template <typename T, typename TW, class F, int SPLIT, int G>
+  void add() {
+    if (count < MAX_CANDIDATES) ks[count++] = Impl<T, TW, F, SPLIT, G>::get();
+  }
+};
+
 template <typename T, typename TW>
-const KernelSet* pick_m(uint32_t m) {
+Candidates candidates_t(uint32_t m) {
+  constexpr bool F32 = std::is_same_v<T, float>;
+  Candidates c;
   switch (m) {
-    case 512: return Impl<T, TW, typename CfgFor<T, 512>::F>::get();
-    case 1024: return Impl<T, TW, typename CfgFor<T, 1024>::F>::get();
-    case 2048: return Impl<T, TW, typename CfgFor<T, 2048>::F>::get();
-    case 4096: return Impl<T, TW, typename CfgFor<T, 4096>::F>::get();
-    default: break;
+    case 512:
+      c.add<T, TW, Fft3<T, 8, 8, 8, 64>, 0, 4>();
+      c.add<T, TW, Fft3<T, 8, 8, 8, 64>, 0, 2>();
+      break;
+    case 1024:
+      c.add<T, TW, Fft3<T, 4, 16, 16, 64>, 0, 4>();
+      c.add<T, TW, Fft3<T, 4, 16, 16, 64>, 0, 2>();
+      break;
+    case 2048:
+      c.add<T, TW, Fft3<T, 8, 16, 16, 128>, 0, 4>();
+      c.add<T, TW, Fft3<T, 8, 16, 16, 128>, 0, 2>();
+      break;
+    case 4096:
+      c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 0, 4>();
+      c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 0, 2>();
+      if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 16, 16, 16, 128>, 0, 4>();
+        c.add<T, TW, Fft3<T, 4, 32, 32, 128>, 0, 4>();
+      }
+      break;
+    case 8192:
+      if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 8, 32, 32, 256>, 0, 4>();
+        c.add<T, TW, Fft3<T, 8, 32, 32, 256>, 0, 2>();
+        c.add<T, TW, Fft3<T, 32, 16, 16, 256>, 0, 4>();
+      } else {
+        c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 1, 4>();
+        c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 1, 2>();
+      }
+      break;
+    case 16384:
+      if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 16, 32, 32, 512>, 0, 4>();
+        c.add<T, TW, Fft3<T, 16, 32, 32, 512>, 0, 2>();
+      }
+      break;
+    case 32768:
+      if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 4>();
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 2>();
+      }
+      break;
+    case 65536:
+      if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 4>();
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 2>();
+      }
+      break;
+    default:
+      break;
   }
-  if constexpr (std::is_same_v<T, float>) {
-    switch (m) {
-      case 8192: return Impl<T, TW, typename CfgFor<T, 8192>::F>::get();
-      case 16384: return Impl<T, TW, typename CfgFor<T, 16384>::F>::get();
-      case 32768: return Impl<T, TW, typename CfgFor<T, 32768>::F>::get();
-      default: break;
-    }
+  return c;
+}
+
+Candidates candidates(bfs_precision p, uint32_t m) {
+  switch (p) {
+    case BFS_FP64: return candidates_t<double, cx<double>>(m);
+    case BFS_FP32: return candidates_t<float, cx<float>>(m);
+    case BFS_FP32_W16F: return candidates_t<float, __half2>(m);
+    case BFS_FP32_W16B: return candidates_t<float, bf16x2>(m);
   }
-  return nullptr;
+  return Candidates{};
 }
 
 const KernelSet* pick_kernels(bfs_precision p, uint32_t m) {
-  switch (p) {
-    case BFS_FP64: return pick_m<double, cx<double>>(m);
-    case BFS_FP32: return pick_m<float, cx<float>>(m);
-    case BFS_FP32_W16F: return pick_m<float, __half2>(m);
-    case BFS_FP32_W16B: return pick_m<float, bf16x2>(m);
-  }
-  return nullptr;
+  const Candidates c = candidates(p, m);
+  return c.count ? c.ks[0] : nullptr;
 }
 
 // ----------------------------------------------------------------- tables --
@@ -187,21 +248,26 @@ void twiddle(uint64_t num, uint64_t den, long double& c, long double& s) {
   s = sinl(ang);
 }
 
+uint64_t table_elems(const KernelSet& ks) {
+  const uint64_t S1 = uint64_t(ks.R2) * ks.R3;
+  return 2ull * (uint64_t(ks.M) + uint64_t(ks.FM) + S1);
+}
+
 template <typename T>
 std::vector<T> make_tables(const KernelSet& ks, uint32_t n) {
-  // layout: tw_u [M] | tw1 [R1][S1] | tw2 [R2][R3], interleaved (re, im)
-  const uint32_t M = ks.M, S1 = ks.R2 * ks.R3;
-  std::vector<T> out(2ull * (M + uint64_t(ks.R1) * S1 + S1));
+  // layout: tw_u [M] (exp(2 pi i k / N)) | tw1 [R1][S1] | tw2 [R2][R3], interleaved (re, im)
+  const uint32_t S1 = ks.R2 * ks.R3;
+  std::vector<T> out(table_elems(ks));
   size_t o = 0;
   long double c, s;
-  for (uint32_t k = 0; k < M; ++k) {
+  for (uint32_t k = 0; k < uint32_t(ks.M); ++k) {
     twiddle(k, n, c, s);
     out[o++] = T(c);
     out[o++] = T(s);
   }
   for (uint32_t n0 = 0; n0 < uint32_t(ks.R1); ++n0)
     for (uint32_t col = 0; col < S1; ++col) {
-      twiddle(uint64_t(n0) * col, M, c, s);
+      twiddle(uint64_t(n0) * col, uint64_t(ks.FM), c, s);
       out[o++] = T(c);
       out[o++] = T(s);
     }
@@ -226,43 +292,89 @@ double linspace_at(double lo, double hi, uint32_t n, uint32_t i) {
 
 bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
+int log2u(uint64_t x) {
+  int l = 0;
+  while ((1ull << l) < x) ++l;
+  return l;
+}
+
+// Capacities of a pooled set of job buffers.
+struct JobNeed {
+  uint64_t ybytes = 0;     // segment spectra, all groups
+  uint64_t zbytes = 0;     // transform scratch of the split group (0 if none)
+  uint64_t sigma = 0;      // S * K doubles
+  uint64_t meta = 0;       // segment table bytes
+};
+
 struct JobBuffers {
-  uint32_t S = 0;
-  void* y = nullptr;          // [S][M] packed complex T
-  double* sigma = nullptr;    // [S][K]
-  tail_rec* tails = nullptr;  // [cap]
+  JobNeed cap;
+  void* y = nullptr;
+  void* z = nullptr;
+  double* sigma = nullptr;
+  tail_rec* tails = nullptr;
   unsigned long long* counter = nullptr;
+  void* meta = nullptr;       // device segment table
+  void* meta_host = nullptr;  // pinned host staging of the table
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t bytes = 0;
+  hipGraphExec_t gexec = nullptr;  // captured job body (graph plans)
+  std::vector<uint64_t> gkey;      // the shape it was captured for
+};
+
+// One resident size of a plan.
+struct SizePlan {
+  uint32_t N = 0, M = 0;
+  const KernelSet* ks = nullptr;  // the chosen candidate
+  int cand = 0, n_cand = 0;
+  float tuned_us[MAX_CANDIDATES] = {};  // measured us per correlation (autotuned plans)
+  void* bank = nullptr;
+  void* tables = nullptr;
+  const void* tw_u = nullptr;
+  const void* tw1 = nullptr;
+  const void* tw2 = nullptr;
+  uint64_t bank_bytes = 0, tab_bytes = 0;
 };
 
 }  // namespace
 
 struct bfs_plan {
   int device = 0;
-  uint32_t N = 0, M = 0, K = 0;
+  uint32_t n_max = 0, n_min = 0, K = 0;
   bfs_precision prec = BFS_FP32;
   double kappa = 0.0;
   uint64_t cap = 0;
-  const KernelSet* ks = nullptr;
-  void* bank = nullptr;
-  void* tables = nullptr;
-  const void* tw_u = nullptr;
-  const void* tw1 = nullptr;
-  const void* tw2 = nullptr;
+  std::vector<SizePlan> sizes;  // ascending N: sizes[i].N = n_min << i
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
+  bool graph = false;
   hipStream_t copy_stream = nullptr;
+  hipStream_t capture_stream = nullptr;
+  std::mutex capture_mu;  // one capture at a time on capture_stream
   std::mutex mu;
   std::vector<JobBuffers*> pool;
   uint64_t live_job_bytes = 0;
   int live_jobs = 0;
 };
 
+namespace {
+
+// Segments of one length within a job.
+struct Group {
+  const SizePlan* sp = nullptr;
+  uint32_t count = 0;
+  uint64_t y_off = 0;     // byte offset of the group's spectra in the job's y buffer
+  uint64_t y_spec = 0;    // byte offset of the group's first segment in job_spectra's output (doubles)
+  uint32_t first = 0;     // index of the group's first entry in the segment table
+};
+
+}  // namespace
+
 struct bfs_job {
   bfs_plan* plan = nullptr;
   JobBuffers* buf = nullptr;
   hipStream_t stream = nullptr;
   uint32_t S = 0;
+  std::vector<Group> groups;
+  std::vector<uint32_t> seg_len;  // per global segment
 };
 
 namespace {
@@ -274,7 +386,7 @@ namespace {
   } while (0)
 
 bfs_status alloc_checked(void** p, uint64_t bytes) {
-  if (hipMalloc(p, bytes) != hipSuccess) {
+  if (hipMalloc(p, bytes ? bytes : 256) != hipSuccess) {
     *p = nullptr;
     (void)hipGetLastError();
     return BFS_ERR_OUT_OF_MEMORY;
@@ -284,10 +396,11 @@ bfs_status alloc_checked(void** p, uint64_t bytes) {
 
 void free_job_buffers(JobBuffers* b) {
   if (!b) return;
-  if (b->y) (void)hipFree(b->y);
-  if (b->sigma) (void)hipFree(b->sigma);
-  if (b->tails) (void)hipFree(b->tails);
-  if (b->counter) (void)hipFree(b->counter);
+  for (void* q : {b->y, b->z, static_cast<void*>(b->sigma), static_cast<void*>(b->tails),
+                  static_cast<void*>(b->counter), b->meta})
+    if (q) (void)hipFree(q);
+  if (b->meta_host) (void)hipHostFree(b->meta_host);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
   delete b;
@@ -297,22 +410,31 @@ void free_plan(bfs_plan* p) {
   if (!p) return;
   for (auto* b : p->pool) free_job_buffers(b);
   p->pool.clear();
-  if (p->bank) (void)hipFree(p->bank);
-  if (p->tables) (void)hipFree(p->tables);
+  for (auto& sp : p->sizes) {
+    if (sp.bank) (void)hipFree(sp.bank);
+    if (sp.tables) (void)hipFree(sp.tables);
+  }
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   delete p;
 }
+
+uint32_t n_min_of(const bfs_plan_desc* d) { return d->n_min ? d->n_min : d->n; }
 
 bfs_status validate(const bfs_plan_desc* d) {
   if (!d) return BFS_ERR_INVALID_ARG;
   if (!is_pow2(d->n) || d->n < 2) return BFS_ERR_INVALID_ARG;
+  const uint32_t nmin = n_min_of(d);
+  if (!is_pow2(nmin) || nmin < 2 || nmin > d->n) return BFS_ERR_INVALID_ARG;
   if (!(d->fs > 0.0) || !std::isfinite(d->fs)) return BFS_ERR_INVALID_ARG;
   if (!(d->kappa >= 0.0) || !std::isfinite(d->kappa)) return BFS_ERR_INVALID_ARG;
   if (d->tail_capacity < 1) return BFS_ERR_INVALID_ARG;
   if (d->precision < BFS_FP64 || d->precision > BFS_FP32_W16B) return BFS_ERR_INVALID_ARG;
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
+  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE)) return BFS_ERR_INVALID_ARG;
+  if (d->candidate > uint32_t(MAX_CANDIDATES)) return BFS_ERR_INVALID_ARG;
   if (d->explicit_templates) {
-    if (d->n_explicit < 1 || d->explicit_len < 1 || d->explicit_len > d->n) return BFS_ERR_INVALID_ARG;
+    if (d->n_explicit < 1 || d->explicit_len < 1 || d->explicit_len > nmin) return BFS_ERR_INVALID_ARG;
   } else {
     if (d->n_f0 < 1 || d->n_fdot < 1) return BFS_ERR_INVALID_ARG;
     if (uint64_t(d->n_f0) * d->n_fdot > 0xffffffffull) return BFS_ERR_INVALID_ARG;
@@ -322,18 +444,105 @@ bfs_status validate(const bfs_plan_desc* d) {
     for (uint32_t i = 0; i < d->n_tau; ++i) {
       if (!(d->tau[i] > 0.0) || !std::isfinite(d->tau[i])) return BFS_ERR_INVALID_ARG;
       const double L = std::nearbyint(d->tau[i] * d->fs);
-      if (L < 1.0 || L > double(d->n)) return BFS_ERR_INVALID_ARG;
+      if (L < 1.0 || L > double(nmin)) return BFS_ERR_INVALID_ARG;
     }
   }
-  if (!pick_kernels(d->precision, d->n / 2)) return BFS_ERR_UNSUPPORTED;
+  for (uint32_t n = nmin; n <= d->n; n <<= 1)
+    if (!pick_kernels(d->precision, n / 2)) return BFS_ERR_UNSUPPORTED;
   return BFS_OK;
 }
 
-bfs_status build_bank(bfs_plan* p, const bfs_plan_desc* d) {
-  const KernelSet& ks = *p->ks;
-  const uint32_t K = p->K, M = p->M;
+// Twiddle tables of kernel set ks into the size's table buffer (sized for
+// every candidate), and the pointers into it.
+bfs_status set_tables(SizePlan& sp, const KernelSet* ks) {
+  const uint64_t bytes = table_elems(*ks) * ks->real_size;
+  hipError_t e;
+  if (ks->real_size == sizeof(double)) {
+    auto tab = make_tables<double>(*ks, sp.N);
+    e = hipMemcpy(sp.tables, tab.data(), bytes, hipMemcpyHostToDevice);
+  } else {
+    auto tab = make_tables<float>(*ks, sp.N);
+    e = hipMemcpy(sp.tables, tab.data(), bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return BFS_ERR_HIP;
+  const char* tb = static_cast<const char*>(sp.tables);
+  sp.ks = ks;
+  sp.tw_u = tb;
+  sp.tw1 = tb + 2ull * sp.M * ks->real_size;
+  sp.tw2 = tb + 2ull * (uint64_t(sp.M) + uint64_t(ks->FM)) * ks->real_size;
+  return BFS_OK;
+}
+
+// Autotuner: time every candidate kernel set of one size on the resident bank
+// (up to 4096 templates against a zero segment spectrum: the work of a
+// correlation does not depend on the data, only the rare tail writes do),
+// best of three launches each, and keep the fastest.
+bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
+  const Candidates c = candidates(p->prec, sp.M);
+  if (c.count < 2) return BFS_OK;
+  const uint32_t Kt = std::min<uint32_t>(p->K, 4096);
+  void* y = nullptr;
+  void* tails = nullptr;
+  void* counter = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const uint64_t ybytes = uint64_t(sp.M) * 2 * sp.ks->real_size;
+  bfs_status st = alloc_checked(&y, ybytes);
+  if (st == BFS_OK) st = alloc_checked(&tails, sizeof(tail_rec));
+  if (st == BFS_OK) st = alloc_checked(&counter, 256);
+  if (st == BFS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = BFS_ERR_HIP;
+  hipStream_t s = p->copy_stream;
+  if (st == BFS_OK && hipMemsetAsync(y, 0, ybytes, s) != hipSuccess) st = BFS_ERR_HIP;
+  int best = 0;
+  float best_ms = 0.f;
+  for (int i = 0; i < c.count && st == BFS_OK; ++i) {
+    st = set_tables(sp, c.ks[i]);
+    if (st != BFS_OK) break;
+    CorrArgs a{};
+    a.bank = sp.bank;
+    a.y = y;
+    a.tw_u = sp.tw_u;
+    a.tw1 = sp.tw1;
+    a.tw2 = sp.tw2;
+    a.K = Kt;
+    a.kappa = p->kappa;
+    a.tails = static_cast<tail_rec*>(tails);
+    a.counter = static_cast<unsigned long long*>(counter);
+    a.cap = 1;
+    float ms_min = 0.f;
+    for (int r = 0; r < 4 && st == BFS_OK; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess || c.ks[i]->corr(false, 1, s, a) != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = BFS_ERR_HIP;
+        break;
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFS_ERR_HIP;
+      if (r == 1 || (r > 1 && ms < ms_min)) ms_min = ms;  // launch 0 warms up
+    }
+    sp.tuned_us[i] = ms_min * 1000.f / float(Kt);
+    if (i == 0 || ms_min < best_ms) {
+      best = i;
+      best_ms = ms_min;
+    }
+  }
+  if (st == BFS_OK) {
+    st = set_tables(sp, c.ks[best]);
+    sp.cand = best;
+  }
+  if (y) (void)hipFree(y);
+  if (tails) (void)hipFree(tails);
+  if (counter) (void)hipFree(counter);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
+}
+
+// Template spectra at every size: per chunk of templates, synthesis (or the
+// explicit samples) + forward transform into scratch, then unpack + scale
+// into the bank rows.
+bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
+  const uint32_t K = p->K;
   const bool expl = d->explicit_templates != nullptr;
-  // per-template parameters (chirps) or the explicit bank, uploaded once
   std::vector<double> f0, fdot;
   std::vector<uint32_t> len;
   void* params = nullptr;
@@ -351,17 +560,18 @@ bfs_status build_bank(bfs_plan* p, const bfs_plan_desc* d) {
     }
     param_bytes = uint64_t(K) * (2 * sizeof(double) + sizeof(uint32_t));
   }
-  // scratch for complex Z of a chunk of templates, plus per-template norms
-  const uint64_t row_bytes = uint64_t(M) * 2 * ks.real_size;
+  // scratch for the complex transforms of a chunk of templates at the largest
+  // size, plus two energy sums per template
+  const uint64_t row_bytes = uint64_t(p->n_max / 2) * 2 * p->sizes.back().ks->real_size;
   const uint64_t avail = p->budget > p->plan_bytes + param_bytes ? p->budget - p->plan_bytes - param_bytes : 0;
-  uint64_t chunk = std::min<uint64_t>(K, std::max<uint64_t>(1, std::min<uint64_t>(4096, avail / (2 * row_bytes + 8))));
-  if (avail < row_bytes + 8) return BFS_ERR_OUT_OF_MEMORY;
+  if (avail < row_bytes + 16) return BFS_ERR_OUT_OF_MEMORY;
+  const uint64_t chunk = std::min<uint64_t>(K, std::max<uint64_t>(1, std::min<uint64_t>(4096, avail / (2 * row_bytes + 16))));
   void* scratch = nullptr;
-  double* norms = nullptr;
+  double* energy = nullptr;
   bfs_status st = alloc_checked(&params, param_bytes);
   if (st != BFS_OK) return st;
   st = alloc_checked(&scratch, chunk * row_bytes);
-  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&norms), chunk * sizeof(double));
+  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&energy), 2 * chunk * sizeof(double));
   hipStream_t s = p->copy_stream;
   bfs_status out = st;
   if (st == BFS_OK) {
@@ -386,24 +596,26 @@ bfs_status build_bank(bfs_plan* p, const bfs_plan_desc* d) {
         dlen = reinterpret_cast<const uint32_t*>(base + 2 * K * sizeof(double));
       }
       bool ok = true;
-      for (uint64_t j0 = 0; j0 < K && ok; j0 += chunk) {
-        const uint32_t nb = uint32_t(std::min<uint64_t>(chunk, K - j0));
-        FwdArgs a{};
-        a.src = params;
-        a.src_stride = expl ? d->explicit_len : 0;
-        a.src_len = expl ? d->explicit_len : 0;
-        a.f0 = df0;
-        a.fdot = dfd;
-        a.len = dlen;
-        a.fs = d->fs;
-        a.taper = int(d->taper);
-        a.first = uint32_t(j0);
-        a.tw1 = p->tw1;
-        a.tw2 = p->tw2;
-        a.out = scratch;
-        a.inv_norm = norms;
-        ok = ks.fwd(expl ? SRC_EXPLICIT : SRC_CHIRP, nb, s, a) == hipSuccess;
-        ok = ok && ks.unpack_bank(nb, s, scratch, p->bank, expl ? nullptr : norms, p->tw_u, j0) == hipSuccess;
+      for (const SizePlan& sp : p->sizes) {
+        for (uint64_t j0 = 0; j0 < K && ok; j0 += chunk) {
+          const uint32_t nb = uint32_t(std::min<uint64_t>(chunk, K - j0));
+          FwdArgs a{};
+          a.src = params;
+          a.src_stride = expl ? d->explicit_len : 0;
+          a.src_len = expl ? d->explicit_len : 0;
+          a.f0 = df0;
+          a.fdot = dfd;
+          a.len = dlen;
+          a.fs = d->fs;
+          a.taper = int(d->taper);
+          a.first = uint32_t(j0);
+          a.tw1 = sp.tw1;
+          a.tw2 = sp.tw2;
+          a.out = scratch;
+          a.energy = energy;
+          ok = sp.ks->fwd(expl ? SRC_EXPLICIT : SRC_CHIRP, nb, s, a) == hipSuccess;
+          ok = ok && sp.ks->unpack_bank(nb, s, scratch, sp.bank, expl ? nullptr : energy, sp.tw_u, j0) == hipSuccess;
+        }
       }
       if (!ok) break;
       if (hipStreamSynchronize(s) != hipSuccess) break;
@@ -412,14 +624,18 @@ bfs_status build_bank(bfs_plan* p, const bfs_plan_desc* d) {
   }
   if (params) (void)hipFree(params);
   if (scratch) (void)hipFree(scratch);
-  if (norms) (void)hipFree(norms);
+  if (energy) (void)hipFree(energy);
   return out;
 }
 
-bfs_status get_job_buffers(bfs_plan* p, uint32_t S, JobBuffers** out) {
+bool covers(const JobNeed& c, const JobNeed& n) {
+  return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta;
+}
+
+bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   std::lock_guard<std::mutex> lk(p->mu);
   for (size_t i = 0; i < p->pool.size(); ++i) {
-    if (p->pool[i]->S >= S) {
+    if (covers(p->pool[i]->cap, need)) {
       *out = p->pool[i];
       p->pool.erase(p->pool.begin() + long(i));
       p->live_job_bytes += (*out)->bytes;
@@ -427,22 +643,37 @@ bfs_status get_job_buffers(bfs_plan* p, uint32_t S, JobBuffers** out) {
       return BFS_OK;
     }
   }
-  const uint64_t ybytes = uint64_t(S) * p->M * 2 * p->ks->real_size;
-  const uint64_t sbytes = uint64_t(S) * p->K * sizeof(double);
+  JobNeed c = need;
+  for (auto* b : p->pool) {  // grow to cover what the pooled sets covered
+    c.ybytes = std::max(c.ybytes, b->cap.ybytes);
+    c.zbytes = std::max(c.zbytes, b->cap.zbytes);
+    c.sigma = std::max(c.sigma, b->cap.sigma);
+    c.meta = std::max(c.meta, b->cap.meta);
+  }
   const uint64_t tbytes = p->cap * sizeof(tail_rec);
-  const uint64_t need = ybytes + sbytes + tbytes + 256;
-  // drop pooled buffers that are too small before asking for new memory
+  uint64_t bytes = c.ybytes + c.zbytes + c.sigma * sizeof(double) + tbytes + c.meta + 256;
+  if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) {
+    c = need;  // the minimal set, after dropping the pool
+    bytes = c.ybytes + c.zbytes + c.sigma * sizeof(double) + tbytes + c.meta + 256;
+  }
   for (auto* b : p->pool) free_job_buffers(b);
   p->pool.clear();
-  if (p->plan_bytes + p->live_job_bytes + need > p->budget) return BFS_ERR_OUT_OF_MEMORY;
+  if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) return BFS_ERR_OUT_OF_MEMORY;
   auto* b = new (std::nothrow) JobBuffers();
   if (!b) return BFS_ERR_OUT_OF_MEMORY;
-  b->S = S;
-  b->bytes = need;
-  bfs_status st = alloc_checked(&b->y, ybytes);
-  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->sigma), sbytes);
+  b->cap = c;
+  b->bytes = bytes;
+  bfs_status st = alloc_checked(&b->y, c.ybytes);
+  if (st == BFS_OK && c.zbytes) st = alloc_checked(&b->z, c.zbytes);
+  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->sigma), c.sigma * sizeof(double));
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->tails), tbytes);
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->counter), 256);
+  if (st == BFS_OK) st = alloc_checked(&b->meta, c.meta);
+  if (st == BFS_OK && hipHostMalloc(&b->meta_host, c.meta ? c.meta : 256, hipHostMallocDefault) != hipSuccess) {
+    b->meta_host = nullptr;
+    (void)hipGetLastError();
+    st = BFS_ERR_OUT_OF_MEMORY;
+  }
   for (int i = 0; i < 4 && st == BFS_OK; ++i)
     if (hipEventCreate(&b->ev[i]) != hipSuccess) st = BFS_ERR_HIP;
   if (st != BFS_OK) {
@@ -462,17 +693,178 @@ void put_job_buffers(bfs_plan* p, JobBuffers* b) {
   p->pool.push_back(b);
 }
 
-// segment spectra: forward real FFT of each segment into the job's Y buffer
-bfs_status queue_segment_fft(bfs_plan* p, const void* y_dev, uint32_t S, void* ybuf, hipStream_t st) {
-  FwdArgs a{};
-  a.src = y_dev;
-  a.src_stride = p->N;
-  a.src_len = p->N;
-  a.tw1 = p->tw1;
-  a.tw2 = p->tw2;
-  a.out = ybuf;
-  HIP_TRY(p->ks->fwd(SRC_SAMPLES, S, st, a));
-  HIP_TRY(p->ks->unpack_y(S, st, ybuf, p->tw_u));
+const SizePlan* size_plan(const bfs_plan* p, uint32_t n) {
+  if (!is_pow2(n) || n < p->n_min || n > p->n_max) return nullptr;
+  return &p->sizes[size_t(log2u(n) - log2u(p->n_min))];
+}
+
+// A prepared job: segments grouped by length (longest first), the segment
+// table (device addresses and global ids per group) staged in pinned memory.
+struct Layout {
+  std::vector<Group> groups;
+  std::vector<uint32_t> seg_len;
+  JobNeed need;
+};
+
+bfs_status make_layout(const bfs_plan* p, const void* y_dev, const uint64_t* offs, const uint32_t* lens,
+                       uint32_t S, Layout& L) {
+  L.seg_len.resize(S);
+  for (uint32_t s = 0; s < S; ++s) {
+    const uint32_t n = lens ? lens[s] : p->n_max;
+    if (!size_plan(p, n)) return BFS_ERR_INVALID_ARG;
+    L.seg_len[s] = n;
+  }
+  (void)y_dev;
+  (void)offs;
+  uint64_t ybytes = 0, zbytes = 0, spec = 0, first = 0;
+  for (int i = int(p->sizes.size()) - 1; i >= 0; --i) {
+    const SizePlan& sp = p->sizes[size_t(i)];
+    uint32_t cnt = 0;
+    for (uint32_t s = 0; s < S; ++s) cnt += (L.seg_len[s] == sp.N);
+    if (!cnt) continue;
+    Group g;
+    g.sp = &sp;
+    g.count = cnt;
+    g.y_off = ybytes;
+    g.first = uint32_t(first);
+    const uint64_t gbytes = uint64_t(cnt) * sp.M * 2 * sp.ks->real_size;
+    ybytes += (gbytes + 255) & ~uint64_t(255);
+    if (sp.ks->split) zbytes = std::max(zbytes, gbytes);
+    first += cnt;
+    L.groups.push_back(g);
+  }
+  // job_spectra output offsets follow global segment order
+  (void)spec;
+  L.need.ybytes = ybytes;
+  L.need.zbytes = zbytes;
+  L.need.sigma = uint64_t(S) * p->K;
+  L.need.meta = uint64_t(S) * (sizeof(uint64_t) + sizeof(uint32_t)) + 256;
+  return BFS_OK;
+}
+
+// Fill the pinned segment table: [S] device addresses in group order, then [S] global ids.
+void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, const Layout& L, void* host) {
+  const uint32_t S = uint32_t(L.seg_len.size());
+  auto* ptrs = static_cast<uint64_t*>(host);
+  auto* ids = reinterpret_cast<uint32_t*>(ptrs + S);
+  const size_t rs = p->sizes[0].ks->real_size;
+  std::vector<uint64_t> off(S);
+  uint64_t acc = 0;
+  for (uint32_t s = 0; s < S; ++s) {
+    off[s] = offs ? offs[s] : acc;
+    acc += L.seg_len[s];
+  }
+  for (const Group& g : L.groups) {
+    uint32_t k = g.first;
+    for (uint32_t s = 0; s < S; ++s) {
+      if (L.seg_len[s] != g.sp->N) continue;
+      ptrs[k] = uint64_t(reinterpret_cast<uintptr_t>(y_dev)) + off[s] * rs;
+      ids[k] = s;
+      ++k;
+    }
+  }
+}
+
+// Queue the body of a job on st: counter reset, table upload, then per group
+// the segment transforms and the fused correlation kernel.  ev[1] / ev[2]
+// bracket the correlation kernels when with_events is set.
+bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
+                        hipStream_t st, bool with_events) {
+  const uint32_t S = uint32_t(L.seg_len.size());
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(1), 0ull);
+  HIP_TRY(hipGetLastError());
+  const uint64_t tbytes = uint64_t(S) * (sizeof(uint64_t) + sizeof(uint32_t));
+  HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, tbytes, hipMemcpyHostToDevice, st));
+  const auto* dptr = static_cast<const uint64_t*>(b->meta);
+  const auto* dids = reinterpret_cast<const uint32_t*>(dptr + S);
+  char* ybase = static_cast<char*>(b->y);
+  for (const Group& g : L.groups) {
+    const KernelSet& ks = *g.sp->ks;
+    FwdArgs a{};
+    a.seg_ptr = dptr + g.first;
+    a.tw1 = g.sp->tw1;
+    a.tw2 = g.sp->tw2;
+    void* yg = ybase + g.y_off;
+    a.out = ks.split ? b->z : yg;
+    HIP_TRY(ks.fwd(SRC_SAMPLES, g.count, st, a));
+    HIP_TRY(ks.unpack_y(g.count, st, a.out, yg, g.sp->tw_u));
+  }
+  if (with_events) HIP_TRY(hipEventRecord(b->ev[1], st));
+  for (const Group& g : L.groups) {
+    CorrArgs c{};
+    c.bank = g.sp->bank;
+    c.y = ybase + g.y_off;
+    c.seg_ids = dids + g.first;
+    c.tw_u = g.sp->tw_u;
+    c.tw1 = g.sp->tw1;
+    c.tw2 = g.sp->tw2;
+    c.K = p->K;
+    c.kappa = p->kappa;
+    c.sigma = dense ? sigma : b->sigma;
+    c.tails = b->tails;
+    c.counter = b->counter;
+    c.cap = dense ? 0 : p->cap;
+    c.rho = rho;
+    HIP_TRY(g.sp->ks->corr(dense, g.count, st, c));
+  }
+  if (with_events) HIP_TRY(hipEventRecord(b->ev[2], st));
+  return BFS_OK;
+}
+
+// Shape of a job as the graph cache sees it: the segment count and, per
+// group, its length and count.  Everything else a replay needs (segment
+// addresses, ids) flows through the pinned table the graph copies from.
+std::vector<uint64_t> graph_key(const Layout& L) {
+  std::vector<uint64_t> k{L.seg_len.size()};
+  for (const Group& g : L.groups) k.push_back((uint64_t(g.sp->N) << 32) | g.count);
+  return k;
+}
+
+// Capture the job body once per job-buffer set and shape on the plan's
+// capture stream, then replay it on st.
+bfs_status launch_graph(bfs_plan* p, JobBuffers* b, const Layout& L, hipStream_t st) {
+  std::vector<uint64_t> key = graph_key(L);
+  if (!b->gexec || b->gkey != key) {
+    if (b->gexec) {
+      (void)hipGraphExecDestroy(b->gexec);
+      b->gexec = nullptr;
+    }
+    std::lock_guard<std::mutex> lk(p->capture_mu);
+    hipStream_t cs = p->capture_stream;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const bfs_status rs = enqueue_body(p, b, L, false, nullptr, nullptr, cs, false);
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (rs != BFS_OK || ec != hipSuccess || !g) {
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return BFS_ERR_HIP;
+    }
+    const hipError_t ei = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      b->gexec = nullptr;
+      return BFS_ERR_HIP;
+    }
+    b->gkey = std::move(key);
+  }
+  HIP_TRY(hipEventRecord(b->ev[1], st));
+  HIP_TRY(hipGraphLaunch(b->gexec, st));
+  HIP_TRY(hipEventRecord(b->ev[2], st));
+  return BFS_OK;
+}
+
+bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
+                     hipStream_t st) {
+  HIP_TRY(hipEventRecord(b->ev[0], st));
+  if (p->graph && !dense) {
+    const bfs_status rs = launch_graph(p, b, L, st);
+    if (rs != BFS_OK) return rs;
+  } else {
+    const bfs_status rs = enqueue_body(p, b, L, dense, rho, sigma, st, true);
+    if (rs != BFS_OK) return rs;
+  }
+  HIP_TRY(hipEventRecord(b->ev[3], st));
   return BFS_OK;
 }
 
@@ -500,13 +892,27 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   auto* p = new (std::nothrow) bfs_plan();
   if (!p) return BFS_ERR_OUT_OF_MEMORY;
   p->device = d->device;
-  p->N = d->n;
-  p->M = d->n / 2;
+  p->n_max = d->n;
+  p->n_min = n_min_of(d);
   p->K = d->explicit_templates ? d->n_explicit : d->n_f0 * d->n_fdot;
   p->prec = d->precision;
   p->kappa = d->kappa;
   p->cap = d->tail_capacity;
-  p->ks = pick_kernels(d->precision, p->M);
+  for (uint32_t n = p->n_min; n <= p->n_max; n <<= 1) {
+    SizePlan sp;
+    sp.N = n;
+    sp.M = n / 2;
+    const Candidates c = candidates(d->precision, sp.M);
+    sp.cand = (d->candidate && int(d->candidate) <= c.count) ? int(d->candidate) - 1 : 0;
+    sp.ks = c.ks[sp.cand];
+    sp.n_cand = c.count;
+    sp.bank_bytes = uint64_t(p->K) * sp.M * sp.ks->spec_size;
+    for (int i = 0; i < c.count; ++i)
+      sp.tab_bytes = std::max<uint64_t>(sp.tab_bytes, table_elems(*c.ks[i]) * c.ks[i]->real_size);
+    p->bank_bytes += sp.bank_bytes;
+    p->plan_bytes += sp.bank_bytes + sp.tab_bytes;
+    p->sizes.push_back(sp);
+  }
   if (hipSetDevice(d->device) != hipSuccess) {
     (void)hipGetLastError();
     delete p;
@@ -518,41 +924,27 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     return BFS_ERR_HIP;
   }
   p->budget = d->hbm_budget_bytes ? std::min<uint64_t>(d->hbm_budget_bytes, free_b) : free_b;
-  if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess) {
-    delete p;
-    return BFS_ERR_HIP;
-  }
-  const KernelSet& ks = *p->ks;
-  p->bank_bytes = uint64_t(p->K) * p->M * ks.spec_size;
-  const size_t n_tab = 2ull * (p->M + uint64_t(ks.R1) * ks.R2 * ks.R3 + uint64_t(ks.R2) * ks.R3);
-  const uint64_t tab_bytes = n_tab * ks.real_size;
-  p->plan_bytes = p->bank_bytes + tab_bytes;
   if (p->plan_bytes > p->budget) {
     free_plan(p);
     return BFS_ERR_OUT_OF_MEMORY;
   }
-  bfs_status st = alloc_checked(&p->bank, p->bank_bytes);
-  if (st == BFS_OK) st = alloc_checked(&p->tables, tab_bytes);
-  if (st != BFS_OK) {
+  p->graph = (d->flags & BFS_PLAN_GRAPH) != 0;
+  if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     free_plan(p);
-    return st;
+    return BFS_ERR_HIP;
   }
-  if (ks.real_size == sizeof(double)) {
-    auto tab = make_tables<double>(ks, p->N);
-    st = hipMemcpy(p->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess ? BFS_OK : BFS_ERR_HIP;
-  } else {
-    auto tab = make_tables<float>(ks, p->N);
-    st = hipMemcpy(p->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice) == hipSuccess ? BFS_OK : BFS_ERR_HIP;
+  bfs_status st = BFS_OK;
+  for (SizePlan& sp : p->sizes) {
+    st = alloc_checked(&sp.bank, sp.bank_bytes);
+    if (st == BFS_OK) st = alloc_checked(&sp.tables, sp.tab_bytes);
+    if (st == BFS_OK) st = set_tables(sp, sp.ks);
+    if (st != BFS_OK) break;
   }
-  if (st != BFS_OK) {
-    free_plan(p);
-    return st;
-  }
-  const char* tb = static_cast<const char*>(p->tables);
-  p->tw_u = tb;
-  p->tw1 = tb + 2ull * p->M * ks.real_size;
-  p->tw2 = tb + 2ull * (p->M + uint64_t(ks.R1) * ks.R2 * ks.R3) * ks.real_size;
-  st = build_bank(p, d);
+  if (st == BFS_OK) st = build_banks(p, d);
+  if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate)
+    for (SizePlan& sp : p->sizes)
+      if (st == BFS_OK) st = tune_size(p, sp);
   if (st != BFS_OK) {
     free_plan(p);
     return st;
@@ -563,57 +955,70 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
 
 bfs_status bfsearch_plan_get_info(const bfs_plan* p, bfs_plan_info* out) {
   if (!p || !out) return BFS_ERR_INVALID_ARG;
-  out->n = p->N;
-  out->m = p->M;
+  out->n = p->n_max;
+  out->m = p->n_max / 2;
   out->k = p->K;
-  out->threads_per_correlation = uint32_t(p->ks->NT);
+  out->threads_per_correlation = uint32_t(p->sizes.back().ks->NT);
   out->bank_bytes = p->bank_bytes;
   out->plan_bytes = p->plan_bytes;
   out->precision = uint32_t(p->prec);
-  out->reserved = 0;
+  out->n_min = p->n_min;
   return BFS_OK;
 }
 
-bfs_status bfsearch_filter(bfs_plan* p, const void* y_dev, uint32_t S, void* hip_stream, bfs_job** out) {
+bfs_status bfsearch_plan_kernel_info(const bfs_plan* p, uint32_t n, bfs_kernel_info* out) {
+  if (!p || !out) return BFS_ERR_INVALID_ARG;
+  const SizePlan* sp = size_plan(p, n ? n : p->n_max);
+  if (!sp) return BFS_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->n = sp->N;
+  out->r1 = uint32_t(sp->ks->R1);
+  out->r2 = uint32_t(sp->ks->R2);
+  out->r3 = uint32_t(sp->ks->R3);
+  out->threads = uint32_t(sp->ks->NT);
+  out->load_group = uint32_t(sp->ks->G);
+  out->split = uint32_t(sp->ks->split);
+  out->candidate = uint32_t(sp->cand);
+  out->n_candidates = uint32_t(sp->n_cand);
+  for (int i = 0; i < MAX_CANDIDATES && i < 8; ++i) out->tuned_us[i] = sp->tuned_us[i];
+  return BFS_OK;
+}
+
+bfs_status bfsearch_filter(bfs_plan* p, const void* y_dev, const uint64_t* seg_offsets, const uint32_t* seg_lengths,
+                           uint32_t S, void* hip_stream, bfs_job** out) {
   if (!out) return BFS_ERR_INVALID_ARG;
   *out = nullptr;
   if (!p || !y_dev || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
-  if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
+  Layout L;
+  bfs_status rs = make_layout(p, y_dev, seg_offsets, seg_lengths, S, L);
+  if (rs != BFS_OK) return rs;
+  auto* j = new (std::nothrow) bfs_job();
+  if (!j) return BFS_ERR_OUT_OF_MEMORY;
+  if (hipSetDevice(p->device) != hipSuccess) {
+    delete j;
+    return BFS_ERR_HIP;
+  }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   JobBuffers* b = nullptr;
-  bfs_status rs = get_job_buffers(p, S, &b);
-  if (rs != BFS_OK) return rs;
-  auto fail = [&](bfs_status e) {
+  rs = get_job_buffers(p, L.need, &b);
+  if (rs != BFS_OK) {
+    delete j;
+    return rs;
+  }
+  stage_table(p, y_dev, seg_offsets, L, b->meta_host);
+  rs = queue_job(p, b, L, false, nullptr, nullptr, st);
+  if (rs != BFS_OK) {
+    (void)hipStreamSynchronize(st);
     put_job_buffers(p, b);
-    return e;
-  };
-  if (hipEventRecord(b->ev[0], st) != hipSuccess) return fail(BFS_ERR_HIP);
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(1), 0ull);
-  if (hipGetLastError() != hipSuccess) return fail(BFS_ERR_HIP);
-  rs = queue_segment_fft(p, y_dev, S, b->y, st);
-  if (rs != BFS_OK) return fail(rs);
-  if (hipEventRecord(b->ev[1], st) != hipSuccess) return fail(BFS_ERR_HIP);
-  CorrArgs a{};
-  a.bank = p->bank;
-  a.y = b->y;
-  a.tw_u = p->tw_u;
-  a.tw1 = p->tw1;
-  a.tw2 = p->tw2;
-  a.K = p->K;
-  a.kappa = p->kappa;
-  a.sigma = b->sigma;
-  a.tails = b->tails;
-  a.counter = b->counter;
-  a.cap = p->cap;
-  if (p->ks->corr(false, S, st, a) != hipSuccess) return fail(BFS_ERR_HIP);
-  if (hipEventRecord(b->ev[2], st) != hipSuccess) return fail(BFS_ERR_HIP);
-  if (hipEventRecord(b->ev[3], st) != hipSuccess) return fail(BFS_ERR_HIP);
-  auto* j = new (std::nothrow) bfs_job();
-  if (!j) return fail(BFS_ERR_OUT_OF_MEMORY);
+    delete j;
+    return rs;
+  }
   j->plan = p;
   j->buf = b;
   j->stream = st;
   j->S = S;
+  j->groups = std::move(L.groups);
+  j->seg_len = std::move(L.seg_len);
   *out = j;
   return BFS_OK;
 }
@@ -665,6 +1070,31 @@ bfs_status bfsearch_job_timing(bfs_job* j, float* corr_ms, float* total_ms) {
   return BFS_OK;
 }
 
+bfs_status bfsearch_job_poll(bfs_job* j, int* done) {
+  if (!j || !done) return BFS_ERR_INVALID_ARG;
+  const hipError_t e = hipEventQuery(j->buf->ev[3]);
+  if (e == hipSuccess) {
+    *done = 1;
+    return BFS_OK;
+  }
+  if (e == hipErrorNotReady) {
+    (void)hipGetLastError();
+    *done = 0;
+    return BFS_OK;
+  }
+  return BFS_ERR_HIP;
+}
+
+bfs_status bfsearch_plan_job_bytes(const bfs_plan* p, const uint32_t* seg_lengths, uint32_t S, uint64_t* bytes) {
+  if (!p || !bytes || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
+  Layout L;
+  const bfs_status rs = make_layout(p, nullptr, nullptr, seg_lengths, S, L);
+  if (rs != BFS_OK) return rs;
+  *bytes = L.need.ybytes + L.need.zbytes + L.need.sigma * sizeof(double) + p->cap * sizeof(tail_rec) + L.need.meta +
+           256;
+  return BFS_OK;
+}
+
 bfs_status bfsearch_job_release(bfs_job* j) {
   if (!j) return BFS_ERR_INVALID_ARG;
   // buffers may be reused by the next filter call: wait for this job's kernels
@@ -686,46 +1116,59 @@ bfs_status bfsearch_destroy(bfs_plan* p) {
   return BFS_OK;
 }
 
-bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t S, void* rho_dev, double* sigma_dev,
-                                    void* hip_stream) {
+bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg_len, uint32_t S, void* rho_dev,
+                                    double* sigma_dev, void* hip_stream) {
   if (!p || !y_dev || !rho_dev || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
+  if (!seg_len) seg_len = p->n_max;
+  if (!size_plan(p, seg_len)) return BFS_ERR_INVALID_ARG;
+  std::vector<uint32_t> lens(S, seg_len);
+  Layout L;
+  bfs_status rs = make_layout(p, y_dev, nullptr, lens.data(), S, L);
+  if (rs != BFS_OK) return rs;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   JobBuffers* b = nullptr;
-  bfs_status rs = get_job_buffers(p, S, &b);
+  rs = get_job_buffers(p, L.need, &b);
   if (rs != BFS_OK) return rs;
-  rs = queue_segment_fft(p, y_dev, S, b->y, st);
-  CorrArgs a{};
-  a.bank = p->bank;
-  a.y = b->y;
-  a.tw_u = p->tw_u;
-  a.tw1 = p->tw1;
-  a.tw2 = p->tw2;
-  a.K = p->K;
-  a.kappa = p->kappa;
-  a.sigma = sigma_dev;
-  a.cap = 0;
-  a.rho = rho_dev;
-  if (rs == BFS_OK && p->ks->corr(true, S, st, a) != hipSuccess) rs = BFS_ERR_HIP;
-  if (rs == BFS_OK && hipEventRecord(b->ev[3], st) != hipSuccess) rs = BFS_ERR_HIP;
+  stage_table(p, y_dev, nullptr, L, b->meta_host);
+  rs = queue_job(p, b, L, true, rho_dev, sigma_dev, st);
   // the buffers go back to the pool only after the queued kernels finish
-  if (rs == BFS_OK) (void)hipEventSynchronize(b->ev[3]);
+  (void)hipStreamSynchronize(st);
   put_job_buffers(p, b);
   return rs;
 }
 
-bfs_status bfsearch_plan_spectra(const bfs_plan* p, uint32_t first, uint32_t count, double* out_dev,
+bfs_status bfsearch_plan_spectra(const bfs_plan* p, uint32_t n, uint32_t first, uint32_t count, double* out_dev,
                                  void* hip_stream) {
   if (!p || !out_dev || count < 1 || uint64_t(first) + count > p->K || count > 65535) return BFS_ERR_INVALID_ARG;
+  const SizePlan* sp = size_plan(p, n ? n : p->n_max);
+  if (!sp) return BFS_ERR_INVALID_ARG;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(p->ks->export_bank(count, static_cast<hipStream_t>(hip_stream), p->bank, out_dev, first));
+  HIP_TRY(sp->ks->export_bank(count, static_cast<hipStream_t>(hip_stream), sp->bank, out_dev, first));
   return BFS_OK;
 }
 
 bfs_status bfsearch_job_spectra(const bfs_job* j, double* out_dev) {
   if (!j || !out_dev) return BFS_ERR_INVALID_ARG;
   if (hipSetDevice(j->plan->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(j->plan->ks->export_y(j->S, j->stream, j->buf->y, out_dev));
+  // output in global segment order: segment s at sum_{s' < s} (N_s'/2 + 1) complex values
+  std::vector<uint64_t> out_off(j->S);
+  uint64_t acc = 0;
+  for (uint32_t s = 0; s < j->S; ++s) {
+    out_off[s] = acc;
+    acc += 2ull * (j->seg_len[s] / 2 + 1);
+  }
+  const char* ybase = static_cast<const char*>(j->buf->y);
+  for (const Group& g : j->groups) {
+    const KernelSet& ks = *g.sp->ks;
+    uint32_t k = 0;
+    for (uint32_t s = 0; s < j->S; ++s) {
+      if (j->seg_len[s] != g.sp->N) continue;
+      const char* row = ybase + g.y_off + uint64_t(k) * g.sp->M * 2 * ks.real_size;
+      HIP_TRY(ks.export_y(1, j->stream, row, out_dev + out_off[s]));
+      ++k;
+    }
+  }
   return BFS_OK;
 }
 

@@ -13,7 +13,8 @@ from .strain import (
     unit_hann_chirp,
     Injection,
 )
-from .workloads import Workload, WORKLOADS, get_workload, make_segment, make_segments
+from .workloads import (Arrival, Workload, WORKLOADS, arrivals, get_workload, make_segment, make_segments,
+                        request_samples)
 
 __all__ = [
     "ENTROPY",
@@ -26,4 +27,7 @@ __all__ = [
     "get_workload",
     "make_segment",
     "make_segments",
+    "Arrival",
+    "arrivals",
+    "request_samples",
 ]

@@ -135,3 +135,49 @@ def make_segments(w: Workload, count: int | None = None, channel: int = 0):
     """List of (samples, injections) for segments 0..count-1 of workload w."""
     count = w.n_segments if count is None else count
     return [make_segment(w, i, channel) for i in range(count)]
+
+
+@dataclass(frozen=True)
+class Arrival:
+    """One request of a served stream: when it arrives, from which channel, its length."""
+
+    index: int
+    time: float        # seconds since the start of the stream
+    channel: int
+    length: int
+    inject: bool       # carries one chirp injection
+
+
+def arrivals(w: Workload, duration_s: float | None = None) -> list[Arrival]:
+    """Poisson arrivals at w.extra['rate_hz'] (all channels together) over duration_s
+    (default w.extra['duration_s']); channel and length uniform, an injection with probability
+    w.extra['inject_rate'].  A shorter duration gives a prefix of a longer one."""
+    rate, channels = float(w.extra["rate_hz"]), int(w.extra["channels"])
+    p_inj = float(w.extra.get("inject_rate", 0.0))
+    dur = float(w.extra["duration_s"] if duration_s is None else duration_s)
+    r = seeded_rng(w.config_id, 0, 0, "arrivals")
+    out: list[Arrival] = []
+    t = 0.0
+    while True:
+        t += float(r.exponential(1.0 / rate))
+        if t >= dur:
+            return out
+        ch = int(r.integers(0, channels))
+        n = int(w.lengths[int(r.integers(0, len(w.lengths)))])
+        inj = bool(r.random() < p_inj)
+        out.append(Arrival(len(out), t, ch, n, inj))
+
+
+def request_samples(w: Workload, a: Arrival) -> tuple[np.ndarray, list[Injection]]:
+    """Samples of one served request (seeded by its channel and index) and its injections."""
+    y = bandlimited_noise(a.length, w.fs, seeded_rng(w.config_id, a.channel, a.index, "noise"))
+    injections: list[Injection] = []
+    if a.inject:
+        tau = 1.0 if 1.0 in w.taus else w.taus[0]
+        injections = draw_injections(seeded_rng(w.config_id, a.channel, a.index, "inject_params"),
+                                     seeded_rng(w.config_id, a.channel, a.index, "offsets"),
+                                     1, a.length, w.fs, tau, w.f0_range, w.fdot_range, w.snr_range)
+        y = add_injections(y, injections, w.fs)
+    if w.dtype == "f32":
+        y = y.astype(np.float32)
+    return y, injections

@@ -83,6 +83,11 @@ def _desc(bfs, **kw):
     ("n_f0", 0),
     ("n_tau", 0),
     ("fdot_hi", float("nan")),
+    ("n_min", 3000),        # not a power of two
+    ("n_min", 1 << 17),     # above n
+    ("n_min", 2048),        # shorter than the 4096-sample templates
+    ("flags", 4),           # unknown flag
+    ("candidate", 99),      # no such kernel candidate
 ])
 def test_plan_rejects_invalid_descriptor(bfs, field, value):
     d, keep = _desc(bfs, **{field: value})
@@ -90,6 +95,15 @@ def test_plan_rejects_invalid_descriptor(bfs, field, value):
     st = bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out))
     assert st == bfs.BFS_ERR_INVALID_ARG
     assert not out.value
+
+
+def test_plan_desc_layout_matches_header(bfs):
+    # field offsets a C compiler gives bfs_plan_desc on x86-64 (natural alignment)
+    off = {f: getattr(bfs.PlanDesc, f).offset for f, _ in bfs.PlanDesc._fields_}
+    assert off["n"] == 0 and off["n_min"] == 4 and off["fs"] == 8
+    assert off["flags"] == off["device"] + 4 and off["candidate"] == off["flags"] + 4
+    assert ctypes.sizeof(bfs.PlanDesc) % 8 == 0
+    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4
 
 
 def test_plan_rejects_template_longer_than_segment(bfs):
@@ -101,7 +115,7 @@ def test_plan_rejects_template_longer_than_segment(bfs):
 
 
 def test_plan_reports_unsupported_sizes(bfs):
-    for n, prec in ((1 << 17, bfs.FP32), (1 << 14, bfs.FP64), (1 << 9, bfs.FP32)):
+    for n, prec in ((1 << 18, bfs.FP32), (1 << 15, bfs.FP64), (1 << 9, bfs.FP32)):
         d, keep = _desc(bfs, n=n, precision=prec)
         taus = np.array([0.1])
         d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -114,10 +128,16 @@ def test_null_handles_are_rejected(bfs):
     out = ctypes.c_void_p()
     nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
     assert lib.bfsearch_plan(None, ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
-    assert lib.bfsearch_filter(None, None, 1, None, ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_filter(None, None, None, None, 1, None, ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_fetch_tails(None, None, 0, ctypes.byref(nw), ctypes.byref(nt)) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_fetch_sigma(None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_job_release(None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_destroy(None) == bfs.BFS_ERR_INVALID_ARG
-    assert lib.bfsearch_correlate_dense(None, None, 1, None, None, None) == bfs.BFS_ERR_INVALID_ARG
-    assert lib.bfsearch_plan_spectra(None, 0, 1, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_correlate_dense(None, None, 0, 1, None, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_plan_spectra(None, 0, 0, 1, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_job_spectra(None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_job_timing(None, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_plan_get_info(None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_plan_kernel_info(None, 0, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_job_poll(None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_plan_job_bytes(None, None, 1, None) == bfs.BFS_ERR_INVALID_ARG

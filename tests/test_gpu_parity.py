@@ -42,7 +42,7 @@ def _oracle_dense(ys, temps):
     return rho, oracle.sigma_time(rho)
 
 
-SIZES = [("f32", 1 << p) for p in range(10, 17)] + [("f64", 1 << p) for p in range(10, 14)]
+SIZES = [("f32", 1 << p) for p in range(10, 18)] + [("f64", 1 << p) for p in range(10, 15)]
 
 
 @pytest.mark.parametrize("prec,n", SIZES, ids=[f"{p}-N{n}" for p, n in SIZES])
@@ -70,9 +70,10 @@ def test_dense_rho_and_sigma_match_oracle(bfs, prec, n):
     assert np.max(np.abs(sig_g - sig_o) / sig_o) <= tol
 
 
-def test_impulse_closed_form_on_gpu(bfs):
-    # y = delta at n0 => rho[n] = w[(n0 - n) mod N] (N = 2^16, FP32)
-    n, n0 = 1 << 16, 12345
+@pytest.mark.parametrize("n", [1 << 16, 1 << 17])
+def test_impulse_closed_form_on_gpu(bfs, n):
+    # y = delta at n0 => rho[n] = w[(n0 - n) mod N] (FP32)
+    n0 = 12345
     w = np.random.default_rng(3).standard_normal(4096)
     y = np.zeros(n, np.float32)
     y[n0] = 1.0
@@ -103,15 +104,36 @@ def test_grid_template_spectra_match_oracle(bfs, prec):
     assert err <= (1e-12 if prec == "f64" else 2e-6), err
 
 
-def test_segment_spectrum_matches_rfft(bfs):
-    w = get_workload("C2")
-    y, _ = make_segment(w, 0)
-    with bfs.Plan(w.n, w.fs, kappa=w.kappa, templates=np.ones((1, 16)), precision="f32") as plan:
+@pytest.mark.parametrize("name", ["C2", "C4"])
+def test_segment_spectrum_matches_rfft(bfs, name):
+    # C2 segment 0: N = 2^16; C4 segment 3: N = 2^17 (the split transform)
+    w = get_workload(name)
+    y, _ = make_segment(w, 3 if name == "C4" else 0)
+    n = len(y)
+    with bfs.Plan(n, w.fs, kappa=w.kappa, templates=np.ones((1, 16)), precision="f32") as plan:
         job = plan.filter(_dev(y, np.float32))
         spec = job.spectra().cpu().numpy()[0]
         job.release()
     ref = np.fft.rfft(y.astype(np.float64))
     assert np.max(np.abs(spec - ref)) <= 2e-6 * np.max(np.abs(ref))
+
+
+def test_template_spectra_at_every_plan_length(bfs):
+    # one plan over 2^14..2^17: the bank at each length is the rfft of the template zero-padded
+    # to that length (durations 0.5, 1 and 2 s as in the batched workload)
+    w = get_workload("C4")
+    grid = bfs.Grid(4, 4, w.f0_range, w.fdot_range, w.taus)
+    f0 = np.repeat(np.linspace(*w.f0_range, 4), 4)
+    fd = np.tile(np.linspace(*w.fdot_range, 4), 4)
+    tau = np.array([w.taus[j % len(w.taus)] for j in range(16)])
+    temps = oracle.template_bank(f0, fd, tau, w.fs)
+    with bfs.Plan(1 << 17, w.fs, kappa=5.0, grid=grid, precision="f32", n_min=1 << 14) as plan:
+        assert plan.n_min == 1 << 14
+        for n in (1 << 14, 1 << 15, 1 << 16, 1 << 17):
+            spec = plan.spectra(n=n).cpu().numpy()
+            ref = np.fft.rfft(np.array([np.pad(t, (0, n - len(t))) for t in temps]), axis=-1)
+            err = max_rel_err(spec, ref, np.max(np.abs(ref), axis=-1))
+            assert err <= 2e-6, (n, err)
 
 
 def _workload_run(bfs, name, n_templates=None):
@@ -285,3 +307,121 @@ def test_repeated_runs_are_bitwise_identical(bfs):
                 res.append((job.fetch_tails()[0], job.fetch_sigma()))
     assert np.array_equal(res[0][0], res[1][0]) and np.array_equal(res[0][1], res[1][1])
     assert len(res[0][0]) > 0
+
+
+def _c4_segments(count):
+    w = get_workload("C4")
+    segs = [make_segment(w, s)[0] for s in range(count)]
+    return w, segs
+
+
+def test_uneven_segments_in_one_call_match_oracle_and_single_calls(bfs):
+    # batching form: segments of 2^14..2^17 samples in one filter call, grouped by length on the
+    # device; every result equals the oracle and equals the same segment filtered alone (bitwise)
+    w, segs = _c4_segments(6)
+    lens = [len(y) for y in segs]
+    assert len(set(lens)) >= 3, lens
+    grid = bfs.Grid(8, 8, w.f0_range, w.fdot_range, w.taus)
+    f0 = np.repeat(np.linspace(*w.f0_range, 8), 8)
+    fd = np.tile(np.linspace(*w.fdot_range, 8), 8)
+    tau = np.array([w.taus[j % len(w.taus)] for j in range(64)])
+    temps = oracle.template_bank(f0, fd, tau, w.fs)
+    flat = np.concatenate(segs).astype(np.float32)
+    with bfs.Plan(1 << 17, w.fs, kappa=w.kappa, grid=grid, precision="f32", n_min=1 << 14) as plan:
+        with plan.filter(torch.from_numpy(flat).cuda(), lengths=lens) as job:
+            tails, total = job.fetch_tails()
+            sig = job.fetch_sigma()
+        alone_t, alone_s = [], []
+        for s, y in enumerate(segs):
+            with plan.filter(_dev(y, np.float32), lengths=[len(y)]) as job:
+                t, _ = job.fetch_tails()
+                t["segment"] = s
+                alone_t.append(t)
+                alone_s.append(job.fetch_sigma()[0])
+    assert total == len(tails)
+    assert np.array_equal(np.concatenate(alone_t), tails)
+    assert np.array_equal(np.stack(alone_s), sig)
+    out = oracle.search([y.astype(np.float64) for y in segs], temps, w.kappa)
+    floor = np.array([[sigma_floor(t, y) for t in temps] for y in segs])
+    assert np.max(np.abs(sig - out["sigma"]) / np.maximum(out["sigma"], floor)) <= TOL["f32"]
+    common, band = compare_tails(tails, out["tails"], out["sigma"], w.kappa, TOL["f32"],
+                                 lambda s, j: oracle.correlate_fft(segs[s].astype(np.float64), temps[j]), floor)
+    print(f"uneven: {total} tails, common {common}, band-only {band}, lengths {lens}")
+    assert common >= 0.99 * len(out["tails"])
+
+
+def test_segment_offsets_select_the_samples(bfs):
+    # segments read at arbitrary element offsets give the packed call's results bitwise
+    n = 4096
+    rng = np.random.default_rng(12)
+    ys = rng.standard_normal((3, n)).astype(np.float32)
+    buf = np.zeros(5 * n + 123, np.float32)
+    offs = [4 * n + 100, 17, 2 * n + 5]
+    for s, o in enumerate(offs):
+        buf[o:o + n] = ys[s]
+    temps = rng.standard_normal((5, 200))
+    with bfs.Plan(n, 4096.0, kappa=2.5, templates=temps, precision="f32") as plan:
+        with plan.filter(_dev(ys, np.float32)) as job:
+            t0, s0 = job.fetch_tails()[0], job.fetch_sigma()
+        with plan.filter(torch.from_numpy(buf).cuda(), lengths=[n] * 3, offsets=offs) as job:
+            t1, s1 = job.fetch_tails()[0], job.fetch_sigma()
+    assert len(t0) > 0 and np.array_equal(t0, t1) and np.array_equal(s0, s1)
+
+
+def test_graph_replays_match_eager(bfs):
+    # a graph plan captures the job once per shape and replays it; every replay (new data each
+    # time, eager torch work and host syncs in between) equals the eager plan bitwise
+    w, segs = _c4_segments(4)
+    lens = [len(y) for y in segs]
+    temps = np.random.default_rng(13).standard_normal((16, 2048))
+    eager = bfs.Plan(1 << 17, w.fs, kappa=4.0, templates=temps, precision="f32", n_min=1 << 14)
+    graph = bfs.Plan(1 << 17, w.fs, kappa=4.0, templates=temps, precision="f32", n_min=1 << 14, graph=True)
+    try:
+        for rep in range(4):
+            flat = torch.from_numpy(np.concatenate(segs).astype(np.float32) * (1.0 + rep)).cuda()
+            _ = torch.randn(1 << 20, device="cuda").sum().item()  # eager work between replays
+            with eager.filter(flat, lengths=lens) as je, graph.filter(flat, lengths=lens) as jg:
+                te, se = je.fetch_tails()[0], je.fetch_sigma()
+                tg, sg = jg.fetch_tails()[0], jg.fetch_sigma()
+            assert len(te) > 0 and np.array_equal(te, tg) and np.array_equal(se, sg), rep
+    finally:
+        eager.close()
+        graph.close()
+
+
+CANDIDATE_SIZES = [1 << 13, 1 << 14, 1 << 16, 1 << 17]
+
+
+@pytest.mark.parametrize("n", CANDIDATE_SIZES, ids=[f"N{n}" for n in CANDIDATE_SIZES])
+def test_every_kernel_candidate_matches_oracle(bfs, n):
+    # the autotuner may pick any candidate: each one is held to the FP32 bar on its own
+    rng = np.random.default_rng(n + 7)
+    y = (rng.standard_normal(n) + 0.25).astype(np.float32)
+    temps = [rng.standard_normal(l) for l in (1, 33, n // 4, n)]
+    bank = np.zeros((len(temps), n))
+    for j, w in enumerate(temps):
+        bank[j, :len(w)] = w
+    rho_o, sig_o = _oracle_dense([y.astype(np.float64)], [b.astype(np.float32).astype(np.float64) for b in bank])
+    with bfs.Plan(n, 4096.0, kappa=5.0, templates=bank, precision="f32") as plan:
+        count = plan.kernel_info()["n_candidates"]
+    assert count >= 2
+    for c in range(1, count + 1):
+        with bfs.Plan(n, 4096.0, kappa=5.0, templates=bank, precision="f32", candidate=c) as plan:
+            info = plan.kernel_info()
+            assert info["candidate"] == c - 1
+            rho_g, sig_g = plan.correlate_dense(_dev(y, np.float32))
+            rho_g, sig_g = rho_g.cpu().numpy(), sig_g.cpu().numpy()
+        err = max_rel_err(rho_g[0], rho_o[0], sig_o[0])
+        print(f"N={n} candidate {info}: max err / sigma = {err:.3e}")
+        assert err <= TOL["f32"] and np.max(np.abs(sig_g - sig_o) / sig_o) <= TOL["f32"]
+
+
+def test_autotuned_plan_reports_timings_and_stays_correct(bfs):
+    w = get_workload("C2")
+    with bfs.Plan(1 << 14, w.fs, kappa=4.5, grid=bfs.Grid(32, 16, w.f0_range, w.fdot_range, (0.5,)),
+                  precision="f32", n_min=1 << 13, autotune=True) as plan:
+        for n in (1 << 13, 1 << 14):
+            info = plan.kernel_info(n)
+            print("autotuned", info)
+            assert len(info["tuned_us"]) == info["n_candidates"] and all(t > 0 for t in info["tuned_us"])
+            assert info["tuned_us"][info["candidate"]] == min(info["tuned_us"])
