@@ -506,7 +506,11 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   cx<T> v[F::P];
-  volatile T ex[F::P], ey[F::P];  // E, kept in scratch memory
+  // E waits in per-thread scratch memory: the array's address escapes into
+  // an empty asm statement, so it stays in memory (ordinary cached scratch
+  // accesses) instead of being promoted to registers, and the asm's memory
+  // clobber orders the stores before everything after it.
+  cx<T> e[F::P];
 
   double acc = 0.0;
   uint32_t cols[F::C1];
@@ -515,10 +519,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 2u, 0u, t);
   const double S0 = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
 #pragma unroll
-  for (int i = 0; i < F::P; ++i) {
-    ex[i] = v[i].x;
-    ey[i] = v[i].y;
-  }
+  for (int i = 0; i < F::P; ++i) e[i] = v[i];
+  asm volatile("" : : "v"(e) : "memory");
   __syncthreads();  // every wave is done with the even half's LDS before the odd half writes it
 
   acc = 0.0;
@@ -538,8 +540,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
       v[c * F::R3 + mp] = cmul(rot<mp, 2 * F::R3, +1>(bc), v[c * F::R3 + mp]);
     });
   }
-  auto z_lo = [&](int i) { return cx<T>{ex[i] + v[i].x, ey[i] + v[i].y}; };
-  auto z_hi = [&](int i) { return cx<T>{ex[i] - v[i].x, ey[i] - v[i].y}; };
+  auto z_lo = [&](int i) { return cadd(e[i], v[i]); };
+  auto z_hi = [&](int i) { return csub(e[i], v[i]); };
   if constexpr (DENSE) {
     const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * K + j) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
     emit_dense<F, T>(z_lo, 0u, N, rr, t);
@@ -549,7 +551,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     T mx = T(0);
 #pragma unroll
     for (int i = 0; i < F::P; ++i) {
-      const T a = ex[i], b = ey[i];
+      const T a = e[i].x, b = e[i].y;
       mx = fmax(mx, fmax(fmax(fabs(a + v[i].x), fabs(b + v[i].y)), fmax(fabs(a - v[i].x), fabs(b - v[i].y))));
     }
     const bool any = (mx > thr) && (rootS > 0.0);

@@ -315,6 +315,9 @@ struct JobBuffers {
   unsigned long long* counter = nullptr;
   void* meta = nullptr;       // device segment table
   void* meta_host = nullptr;  // pinned host staging of the table
+  unsigned long long* count_host = nullptr;  // pinned copy of the tail counter, written by the job
+  bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
+  uint64_t tails_host_cap = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   uint64_t bytes = 0;
   hipGraphExec_t gexec = nullptr;  // captured job body (graph plans)
@@ -400,6 +403,8 @@ void free_job_buffers(JobBuffers* b) {
                   static_cast<void*>(b->counter), b->meta})
     if (q) (void)hipFree(q);
   if (b->meta_host) (void)hipHostFree(b->meta_host);
+  if (b->count_host) (void)hipHostFree(b->count_host);
+  if (b->tails_host) (void)hipHostFree(b->tails_host);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
@@ -669,8 +674,9 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->tails), tbytes);
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->counter), 256);
   if (st == BFS_OK) st = alloc_checked(&b->meta, c.meta);
-  if (st == BFS_OK && hipHostMalloc(&b->meta_host, c.meta ? c.meta : 256, hipHostMallocDefault) != hipSuccess) {
-    b->meta_host = nullptr;
+  if (st == BFS_OK && (hipHostMalloc(&b->meta_host, c.meta ? c.meta : 256, hipHostMallocDefault) != hipSuccess ||
+                       hipHostMalloc(reinterpret_cast<void**>(&b->count_host), 256, hipHostMallocDefault) !=
+                           hipSuccess)) {
     (void)hipGetLastError();
     st = BFS_ERR_OUT_OF_MEMORY;
   }
@@ -808,6 +814,8 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     HIP_TRY(g.sp->ks->corr(dense, g.count, st, c));
   }
   if (with_events) HIP_TRY(hipEventRecord(b->ev[2], st));
+  // the tail count travels with the job, so a fetch needs one copy only
+  HIP_TRY(hipMemcpyAsync(b->count_host, b->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   return BFS_OK;
 }
 
@@ -1027,25 +1035,36 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
                                 uint64_t* n_total) {
   if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
   bfs_plan* p = j->plan;
+  JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(hipStreamWaitEvent(p->copy_stream, j->buf->ev[3], 0));
-  unsigned long long count = 0;
-  HIP_TRY(hipMemcpyAsync(&count, j->buf->counter, sizeof(count), hipMemcpyDeviceToHost, p->copy_stream));
-  HIP_TRY(hipStreamSynchronize(p->copy_stream));
+  HIP_TRY(hipEventSynchronize(b->ev[3]));
+  const unsigned long long count = *b->count_host;
   const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
-  std::vector<bfs_tail> tmp(on_dev);
+  if (on_dev > b->tails_host_cap) {
+    if (b->tails_host) (void)hipHostFree(b->tails_host);
+    b->tails_host = nullptr;
+    b->tails_host_cap = 0;
+    const uint64_t want = std::min<uint64_t>(p->cap, std::max<uint64_t>(on_dev, 2 * on_dev));
+    if (hipHostMalloc(reinterpret_cast<void**>(&b->tails_host), want * sizeof(bfs_tail), hipHostMallocDefault) !=
+        hipSuccess) {
+      b->tails_host = nullptr;
+      (void)hipGetLastError();
+      return BFS_ERR_OUT_OF_MEMORY;
+    }
+    b->tails_host_cap = want;
+  }
+  bfs_tail* tmp = b->tails_host;
   if (on_dev) {
-    HIP_TRY(hipMemcpyAsync(tmp.data(), j->buf->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost,
-                           p->copy_stream));
+    HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
     HIP_TRY(hipStreamSynchronize(p->copy_stream));
   }
-  std::sort(tmp.begin(), tmp.end(), [](const bfs_tail& a, const bfs_tail& b) {
-    if (a.segment != b.segment) return a.segment < b.segment;
-    if (a.template_id != b.template_id) return a.template_id < b.template_id;
-    return a.lag < b.lag;
+  std::sort(tmp, tmp + on_dev, [](const bfs_tail& a, const bfs_tail& c) {
+    if (a.segment != c.segment) return a.segment < c.segment;
+    if (a.template_id != c.template_id) return a.template_id < c.template_id;
+    return a.lag < c.lag;
   });
   const uint64_t nw = std::min<uint64_t>(on_dev, capacity);
-  if (nw) std::memcpy(out_host, tmp.data(), nw * sizeof(bfs_tail));
+  if (nw) std::memcpy(out_host, tmp, nw * sizeof(bfs_tail));
   *n_written = nw;
   *n_total = count;
   return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
