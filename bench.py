@@ -82,6 +82,8 @@ def parse():
     p.add_argument("--copy-calibration-mib", type=int, default=0,
                    help="also run a plain torch copy of this size (HBM counter calibration)")
     p.add_argument("--no-batched", action="store_true")
+    p.add_argument("--no-dense-bank", action="store_true")
+    p.add_argument("--depth", type=int, default=2, help="filter calls in flight in the step loop")
     p.add_argument("--no-serving", action="store_true")
     p.add_argument("--batched-steps", type=int, default=5)
     p.add_argument("--serve-seconds", type=float, default=30.0,
@@ -94,28 +96,45 @@ def parse():
     return p.parse_args()
 
 
-def run_plan(bfs, torch, w, y_dev, precision, steps, warmup):
+def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2):
+    """Plan the workload, then time `steps` steps.  A step is one filter call (segment FFT +
+    fused kernel over every template) and the fetch of its sorted tails; up to `depth` steps are
+    in flight, so the next step's kernels run while the host fetches and sorts the last one's
+    tails.  Every timed step completes inside the timed region."""
+    from collections import deque
+
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
     t0 = time.perf_counter()
-    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision)
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision, tail_capacity=1 << 22)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    for _ in range(warmup):
-        with plan.filter(y_dev) as job:
-            job.fetch_tails()
-    torch.cuda.synchronize()
     corr_ms, job_ms, lat_ms, n_tails = [], [], [], 0
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ts = time.perf_counter()
-        job = plan.filter(y_dev)
-        tails, total = job.fetch_tails()
+
+    def finish(item):
+        nonlocal n_tails
+        job, ts = item
+        _, total = job.fetch_tails()
         lat_ms.append((time.perf_counter() - ts) * 1e3)
         c, t = job.timing()
         corr_ms.append(c)
         job_ms.append(t)
         n_tails = total
         job.release()
+
+    def loop(n):
+        q = deque()
+        for _ in range(n):
+            q.append((plan.filter(y_dev), time.perf_counter()))
+            if len(q) >= depth:
+                finish(q.popleft())
+        while q:
+            finish(q.popleft())
+
+    loop(warmup)
+    torch.cuda.synchronize()
+    corr_ms.clear(), job_ms.clear(), lat_ms.clear()
+    t0 = time.perf_counter()
+    loop(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = {"bank_bytes": plan.bank_bytes, "threads": plan.threads_per_correlation,
@@ -166,6 +185,23 @@ def run_batched(bfs, torch, steps, warmup):
            "kernels": kernels}
     plan.close()
     return out
+
+
+def run_dense_bank(bfs, torch, steps, warmup):
+    """C3: the C2 segment against all 1,048,576 chirps (1024 f0 x 1024 fdot), kappa 5.5, with FP16
+    spectra resident (128 GiB; FP32 would take 256 GiB of the 288 GB)."""
+    import numpy as np
+    from synthetic import get_workload, make_segment
+
+    w = get_workload("C3")
+    y, _ = make_segment(w, 0)
+    y_dev = torch.from_numpy(np.ascontiguousarray(y[None, :])).to(device="cuda:0", dtype=torch.float32)
+    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, "f32-w16f", steps, warmup)
+    k = w.n_templates
+    return {"workload": f"C3: {w.description}", "precision": "f32-w16f", "value": steps * k / wall,
+            "unit": "correlations/s", "kernel_rate": k / (float(np.mean(corr_ms)) * 1e-3),
+            "ms_per_step": wall / steps * 1e3, "bank_bytes": info["bank_bytes"], "bank_build_s": build_s,
+            "tails_per_step": n_tails}
 
 
 def run_serving(bfs, torch, args):
@@ -251,7 +287,7 @@ def main():
     y_dev = torch.from_numpy(np.ascontiguousarray(y[None, :])).to(device="cuda:0", dtype=dt)
 
     wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, args.precision,
-                                                             args.steps, args.warmup)
+                                                             args.steps, args.warmup, args.depth)
     k = w.n_templates
     value = args.steps * k / wall
     corr_avg_s = float(np.mean(corr_ms)) * 1e-3
@@ -288,6 +324,7 @@ def main():
         },
         "kernel_rate": k / corr_avg_s,
         "nominal_tflops": nominal_flops(w.n) * value / 1e12,
+        "pipeline_depth": args.depth,
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(np.max(lat_ms))},
         "job_device_ms": info["job_device_ms"],
@@ -297,7 +334,7 @@ def main():
     }
     if not args.no_fp16 and args.precision == "f32":
         wall16, build16, corr16, lat16, _, info16 = run_plan(bfs, torch, w, y_dev, "f32-w16f",
-                                                             args.steps, args.warmup)
+                                                             args.steps, args.warmup, args.depth)
         line["fp16_spectra"] = {"value": args.steps * k / wall16, "kernel_rate": k / (np.mean(corr16) * 1e-3),
                                 "ms_per_step": wall16 / args.steps * 1e3, "bank_build_s": build16,
                                 "bank_bytes": info16["bank_bytes"]}
@@ -311,6 +348,8 @@ def main():
         _ = float(a.sum())
         torch.cuda.synchronize()
         line["calibration_bytes"] = nbytes
+    if not args.no_dense_bank and args.workload == "C2":
+        line["dense_bank_fp16"] = run_dense_bank(bfs, torch, 3, 1)
     if not args.no_batched and args.workload == "C2":
         line["batched"] = run_batched(bfs, torch, args.batched_steps, 1)
     if not args.no_serving and args.workload == "C2":

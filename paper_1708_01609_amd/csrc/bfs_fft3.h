@@ -57,6 +57,15 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup barrier for LDS traffic only: every wave's LDS accesses have
+// completed before any wave passes it, and the compiler moves no memory
+// access across it.  Unlike __syncthreads it does not wait for the wave's
+// outstanding global stores (its release fence would), so stores issued
+// before it keep draining while the workgroup goes on.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Phase boundary: no instruction and no memory access moves across it, which
 // bounds how many loads the compiler keeps in flight (and registers live).
 __device__ __forceinline__ void sched_fence() {

@@ -124,11 +124,11 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     if ((t & 63) == 0) red[t >> 6] = s;
   }
   fft3_ex1_write<F, 0>(v, lds, cols);
-  __syncthreads();
+  lds_barrier();
   fft3_ex1_read<F, 0>(v, lds, t);
-  __syncthreads();
+  lds_barrier();
   fft3_ex1_write<F, 1>(v, lds, cols);
-  __syncthreads();
+  lds_barrier();
   fft3_ex1_read<F, 1>(v, lds, t);
   if constexpr (SRC == SRC_CHIRP) {
     if (t == 0) {
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
       energy[b] = s;
     }
   }
-  __syncthreads();
+  lds_barrier();
   fft3_pass2<F, -1>(v, tw2, t);
   fft3_ex2<F>(v, lds, t);
   fft3_pass3<F, -1>(v);
@@ -360,16 +360,16 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
     if ((t & 63) == 0) red[t >> 6] = ws;
   }
   fft3_ex1_write<F, 0>(v, lds, cols);
-  __syncthreads();
+  lds_barrier();
   double S = 0.0;
 #pragma unroll
   for (int w = 0; w < F::NW; ++w) S += red[w];
   fft3_ex1_read<F, 0>(v, lds, t);
-  __syncthreads();
+  lds_barrier();
   fft3_ex1_write<F, 1>(v, lds, cols);
-  __syncthreads();
+  lds_barrier();
   fft3_ex1_read<F, 1>(v, lds, t);
-  __syncthreads();
+  lds_barrier();
   fft3_pass2<F, +1>(v, tw2, t);
   fft3_ex2<F>(v, lds, t);
   fft3_pass3<F, +1>(v);
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
 #pragma unroll
   for (int i = 0; i < F::P; ++i) e[i] = v[i];
   asm volatile("" : : "v"(e) : "memory");
-  __syncthreads();  // every wave is done with the even half's LDS before the odd half writes it
+  lds_barrier();  // every wave is done with the even half's LDS before the odd half writes it
 
   acc = 0.0;
 #pragma unroll

@@ -425,3 +425,28 @@ def test_autotuned_plan_reports_timings_and_stays_correct(bfs):
             print("autotuned", info)
             assert len(info["tuned_us"]) == info["n_candidates"] and all(t > 0 for t in info["tuned_us"])
             assert info["tuned_us"][info["candidate"]] == min(info["tuned_us"])
+
+
+@pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"])
+def test_c3_full_dense_bank_16bit_against_oracle_subset(bfs, prec):
+    # C3: the C2 segment against all 1,048,576 chirps with 16-bit spectra resident (128 GiB);
+    # sigma and tails of templates 0..4095 against the FP64 oracle at the 16-bit tolerance
+    w = get_workload("C3")
+    y, _ = make_segment(w, 0)
+    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
+    f0, fd, tau = w.template_params()
+    ids = np.arange(4096)
+    temps = oracle.template_bank(f0, fd, tau, w.fs, ids=ids)
+    out = oracle.search([y.astype(np.float64)], temps, w.kappa)
+    with bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=prec, tail_capacity=1 << 22) as plan:
+        assert plan.k == 1 << 20 and plan.bank_bytes == (1 << 20) * (w.n // 2) * 4
+        with plan.filter(_dev(y, np.float32)) as job:
+            tails, total = job.fetch_tails()
+            sig = job.fetch_sigma()[:, :4096]
+    sub = tails[tails["template"] < 4096]
+    floor = np.array([[sigma_floor(t, y) for t in temps]])
+    scale = np.maximum(out["sigma"], floor)
+    assert np.max(np.abs(sig - out["sigma"]) / scale) <= TOL[prec]
+    common, band = compare_tails(sub, out["tails"], out["sigma"], w.kappa, TOL[prec],
+                                 lambda s, j: oracle.correlate_fft(y.astype(np.float64), temps[j]), floor)
+    print(f"C3 {prec}: {total} tails over 2^20 templates; subset common {common}, band-only {band}")
