@@ -36,7 +36,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
 # for the kernel sources they were taken on (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "592dd8c611d975a5": {"f32": 2.1941e9, "f32-w16f": 1.0845e9},
+    "77e6e2cec26f377f": {"f32": 2.1999e9, "f32-w16f": 1.0908e9},
 }
 
 
