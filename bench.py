@@ -99,8 +99,9 @@ def parse():
 def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2):
     """Plan the workload, then time `steps` steps.  A step is one filter call (segment FFT +
     fused kernel over every template) and the fetch of its sorted tails; up to `depth` steps are
-    in flight, so the next step's kernels run while the host fetches and sorts the last one's
-    tails.  Every timed step completes inside the timed region."""
+    queued on the stream, so the next step's kernels run while the host fetches and sorts the
+    last one's tails (two concurrent streams measured slower: their kernels compete for the
+    CUs).  Every timed step completes inside the timed region."""
     from collections import deque
 
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
@@ -123,7 +124,7 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2):
 
     def loop(n):
         q = deque()
-        for _ in range(n):
+        for i in range(n):
             q.append((plan.filter(y_dev), time.perf_counter()))
             if len(q) >= depth:
                 finish(q.popleft())

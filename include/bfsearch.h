@@ -61,9 +61,11 @@ typedef enum {
 /* Plan flags. */
 #define BFS_PLAN_GRAPH 1u    /* capture each job shape once as a HIP graph and
                                 replay it (fewer launches per filter call) */
-#define BFS_PLAN_AUTOTUNE 2u /* at plan time, time every kernel candidate of
-                                each segment length on the resident bank and
-                                keep the fastest (default: the first) */
+#define BFS_PLAN_AUTOTUNE 2u /* at plan time, time every kernel candidate and
+                                every segment tile of each length on the
+                                resident bank and keep the fastest (default:
+                                the first candidate; the tile whose segment
+                                spectra fill half an XCD's L2) */
 
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
@@ -112,6 +114,8 @@ typedef struct {
   uint32_t candidate;           /* 0: the default kernel (or the autotuned
                                    one); i > 0: candidate i - 1 at every length
                                    that has that many (manual tuning, tests) */
+  uint32_t tile;                /* 0: the default (or autotuned) segment tile;
+                                   t > 0: t segments per tile at every length */
 } bfs_plan_desc;
 
 /* Read-only facts about a plan. */
@@ -135,6 +139,13 @@ typedef struct {
   uint32_t n_candidates;        /* candidates built for this length */
   float tuned_us[8];            /* per candidate: measured microseconds per
                                    correlation (BFS_PLAN_AUTOTUNE), else 0 */
+  uint32_t tile;                /* segments per tile of the workgroup order: the
+                                   workgroups of one template and `tile` segments
+                                   run back to back on one XCD, which serves the
+                                   template's spectrum from its L2 */
+  float tile_us[5];             /* measured microseconds per correlation for tiles
+                                   1, 2, 4, 8, 16 on 16 segments (BFS_PLAN_AUTOTUNE),
+                                   else 0 */
 } bfs_kernel_info;
 
 /* Build a plan: synthesises every template on the device (FP64 phase and

@@ -57,6 +57,7 @@ class PlanDesc(ctypes.Structure):
         ("device", ctypes.c_int),
         ("flags", ctypes.c_uint32),
         ("candidate", ctypes.c_uint32),
+        ("tile", ctypes.c_uint32),
     ]
 
 
@@ -72,6 +73,8 @@ class KernelInfo(ctypes.Structure):
         ("candidate", ctypes.c_uint32),
         ("n_candidates", ctypes.c_uint32),
         ("tuned_us", ctypes.c_float * 8),
+        ("tile", ctypes.c_uint32),
+        ("tile_us", ctypes.c_float * 5),
     ]
 
 
@@ -159,7 +162,7 @@ class Plan:
                  templates: np.ndarray | None = None, precision: str = "f32",
                  tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
                  n_min: int | None = None, graph: bool = False, autotune: bool = False,
-                 candidate: int = 0):
+                 candidate: int = 0, tile: int = 0):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
         d.n_min = int(n_min) if n_min else 0
@@ -167,6 +170,7 @@ class Plan:
         d.tail_capacity, d.hbm_budget_bytes, d.device = int(tail_capacity), int(hbm_budget_bytes), int(device)
         d.flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
         d.candidate = int(candidate)
+        d.tile = int(tile)
         keep = []
         if templates is not None:
             t = np.ascontiguousarray(np.atleast_2d(np.asarray(templates, dtype=np.float64)))
@@ -203,7 +207,8 @@ class Plan:
         _check(_lib.bfsearch_plan_kernel_info(self._h, int(n or 0), ctypes.byref(ki)), "bfsearch_plan_kernel_info")
         return {"n": ki.n, "radices": (ki.r1, ki.r2, ki.r3), "threads": ki.threads, "load_group": ki.load_group,
                 "split": bool(ki.split), "candidate": ki.candidate, "n_candidates": ki.n_candidates,
-                "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)]}
+                "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)],
+                "tile": ki.tile, "tile_us": {t: float(ki.tile_us[i]) for i, t in enumerate((1, 2, 4, 8, 16))}}
 
     def job_bytes(self, lengths) -> int:
         """Device bytes a filter call over segments of these lengths holds while live."""

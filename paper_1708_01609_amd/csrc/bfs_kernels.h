@@ -436,8 +436,38 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool an
   }
 }
 
-// One workgroup per (template j = blockIdx.x, spectrum row blockIdx.y).
-//   bank  [K][M] packed template spectra (storage TW), yspec [rows][M] packed;
+// Workgroup order.  The hardware hands workgroups to the 8 XCDs round robin
+// (b mod 8), so XCD x runs b = x, x + 8, x + 16, ...  Within an XCD the order
+// is: tile of T segments, then template j = 8 jj + x, then the segment within
+// the tile.  The T workgroups of one template run back to back on one XCD and
+// read its bank row from that XCD's L2, while the tile's T segment spectra stay
+// L2-resident as the tile sweeps the templates (T = 1: every template once per
+// segment, the segment spectrum shared by all).  Returns false for the padding
+// workgroups when K is not a multiple of 8.  Requires 1 <= T <= S.
+__device__ __forceinline__ bool tile_map(uint32_t b, uint32_t K, uint32_t S, uint32_t T, uint32_t& j,
+                                         uint32_t& row) {
+  const uint32_t x = b & 7u, i = b >> 3;
+  const uint32_t kx = (K + 7u - x) >> 3;  // templates with j = x (mod 8)
+  if (i >= kx * S) return false;
+  const uint32_t full = S / T, per_tile = kx * T;
+  uint32_t jj, s;
+  if (i < full * per_tile) {
+    const uint32_t ti = i / per_tile, rem = i - ti * per_tile;
+    jj = rem / T;
+    s = ti * T + (rem - jj * T);
+  } else {
+    const uint32_t r = S - full * T, rem = i - full * per_tile;
+    jj = rem / r;
+    s = full * T + (rem - jj * r);
+  }
+  j = 8u * jj + x;
+  row = s;
+  return true;
+}
+
+// One workgroup per (template j, spectrum row), in the order of tile_map over
+// a 1-D grid of 8 ceil(K/8) n_rows workgroups.
+//   bank  [K][M] packed template spectra (storage TW), yspec [n_rows][M] packed;
 //   row r is segment seg_ids[r] (or r), the id used for sigma and tails.
 //   tw_u  exp(+2 pi i k / N), tw1/tw2 the FFT twiddles (see bfs_fft3.h).
 // z = IDFT_M(Z) gives z_n = N (rho_{2n} + i rho_{2n+1}); with
@@ -447,7 +477,7 @@ template <typename T, typename TW, class F, bool DENSE, int G>
 __global__ __launch_bounds__(F::NT) void corr_kernel(
     const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    uint32_t K, double kappa, double* __restrict__ sigma_out,
+    uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     T* __restrict__ rho_dense) {
   constexpr int M = F::M;
@@ -455,7 +485,8 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
-  const uint32_t j = blockIdx.x, row = blockIdx.y;
+  uint32_t j, row;
+  if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
   const uint32_t s = seg_ids ? seg_ids[row] : row;
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
@@ -493,7 +524,7 @@ template <typename T, typename TW, class F, bool DENSE, int G>
 __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    uint32_t K, double kappa, double* __restrict__ sigma_out,
+    uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     T* __restrict__ rho_dense) {
   constexpr int H = F::M, M = 2 * H;
@@ -501,7 +532,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
-  const uint32_t j = blockIdx.x, row = blockIdx.y;
+  uint32_t j, row;
+  if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
   const uint32_t s = seg_ids ? seg_ids[row] : row;
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));

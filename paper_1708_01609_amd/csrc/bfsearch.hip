@@ -55,6 +55,7 @@ struct CorrArgs {
   const void* tw1;
   const void* tw2;
   uint32_t K;
+  uint32_t tile;            // segments per tile of the workgroup order (1 <= tile <= rows)
   double kappa;
   double* sigma;
   tail_rec* tails;
@@ -114,7 +115,7 @@ struct Impl {
     return hipGetLastError();
   }
   template <bool DENSE>
-  static void launch_corr(dim3 grid, hipStream_t st, const CorrArgs& a) {
+  static void launch_corr(dim3 grid, uint32_t S, uint32_t tile, hipStream_t st, const CorrArgs& a) {
     const auto* bank = static_cast<const TW*>(a.bank);
     const auto* y = static_cast<const cx<T>*>(a.y);
     const auto* tu = static_cast<const cx<T>*>(a.tw_u);
@@ -123,17 +124,21 @@ struct Impl {
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
     if constexpr (SPLIT)
       hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
     else
       hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
   }
+  // 1-D grid in the XCD-aware order of tile_map: 8 ceil(K/8) S workgroups
   static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    const dim3 grid(a.K, S);
+    const uint64_t blocks = 8ull * ((uint64_t(a.K) + 7) / 8) * S;
+    if (!S || blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    const uint32_t tile = std::min<uint32_t>(std::max<uint32_t>(a.tile, 1u), S);
+    const dim3 grid(static_cast<uint32_t>(blocks));
     if (dense)
-      launch_corr<true>(grid, st, a);
+      launch_corr<true>(grid, S, tile, st, a);
     else
-      launch_corr<false>(grid, st, a);
+      launch_corr<false>(grid, S, tile, st, a);
     return hipGetLastError();
   }
   static hipError_t export_bank(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first) {
@@ -156,6 +161,14 @@ struct Impl {
 };
 
 constexpr int MAX_CANDIDATES = 8;
+constexpr int N_TILES = 5;
+constexpr uint32_t TILES[N_TILES] = {1, 2, 4, 8, 16};
+
+// Default segments per tile: as many segment spectra as fill half of one XCD's 4 MiB L2.
+uint32_t default_tile(const KernelSet& ks) {
+  const uint64_t row = uint64_t(ks.M) * 2 * ks.real_size;
+  return uint32_t(std::max<uint64_t>(1, (2ull << 20) / row));
+}
 
 struct Candidates {
   const KernelSet* ks[MAX_CANDIDATES];
@@ -330,6 +343,8 @@ struct SizePlan {
   const KernelSet* ks = nullptr;  // the chosen candidate
   int cand = 0, n_cand = 0;
   float tuned_us[MAX_CANDIDATES] = {};  // measured us per correlation (autotuned plans)
+  uint32_t tile = 1;                    // segments per tile of the workgroup order
+  float tile_us[N_TILES] = {};          // measured us per correlation for TILES[i] (autotuned plans)
   void* bank = nullptr;
   void* tables = nullptr;
   const void* tw_u = nullptr;
@@ -438,6 +453,7 @@ bfs_status validate(const bfs_plan_desc* d) {
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
   if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE)) return BFS_ERR_INVALID_ARG;
   if (d->candidate > uint32_t(MAX_CANDIDATES)) return BFS_ERR_INVALID_ARG;
+  if (d->tile > 65535) return BFS_ERR_INVALID_ARG;
   if (d->explicit_templates) {
     if (d->n_explicit < 1 || d->explicit_len < 1 || d->explicit_len > nmin) return BFS_ERR_INVALID_ARG;
   } else {
@@ -481,10 +497,10 @@ bfs_status set_tables(SizePlan& sp, const KernelSet* ks) {
 // Autotuner: time every candidate kernel set of one size on the resident bank
 // (up to 4096 templates against a zero segment spectrum: the work of a
 // correlation does not depend on the data, only the rare tail writes do),
-// best of three launches each, and keep the fastest.
+// best of three launches each, and keep the fastest; then, with that kernel,
+// time every segment tile of the workgroup order on 16 segments.
 bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
   const Candidates c = candidates(p->prec, sp.M);
-  if (c.count < 2) return BFS_OK;
   const uint32_t Kt = std::min<uint32_t>(p->K, 4096);
   void* y = nullptr;
   void* tails = nullptr;
@@ -499,7 +515,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
   if (st == BFS_OK && hipMemsetAsync(y, 0, ybytes, s) != hipSuccess) st = BFS_ERR_HIP;
   int best = 0;
   float best_ms = 0.f;
-  for (int i = 0; i < c.count && st == BFS_OK; ++i) {
+  for (int i = 0; i < c.count && c.count > 1 && st == BFS_OK; ++i) {
     st = set_tables(sp, c.ks[i]);
     if (st != BFS_OK) break;
     CorrArgs a{};
@@ -533,6 +549,43 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
   if (st == BFS_OK) {
     st = set_tables(sp, c.ks[best]);
     sp.cand = best;
+  }
+  if (y) (void)hipFree(y);
+  y = nullptr;
+  // tile of the workgroup order, timed on TUNE_SEGS zero segment spectra
+  constexpr uint32_t TUNE_SEGS = 16;
+  if (st == BFS_OK) st = alloc_checked(&y, TUNE_SEGS * ybytes);
+  if (st == BFS_OK && hipMemsetAsync(y, 0, TUNE_SEGS * ybytes, s) != hipSuccess) st = BFS_ERR_HIP;
+  float best_tile_ms = 0.f;
+  for (int i = 0; i < N_TILES && st == BFS_OK; ++i) {
+    CorrArgs a{};
+    a.bank = sp.bank;
+    a.y = y;
+    a.tw_u = sp.tw_u;
+    a.tw1 = sp.tw1;
+    a.tw2 = sp.tw2;
+    a.K = Kt;
+    a.tile = TILES[i];
+    a.kappa = p->kappa;
+    a.tails = static_cast<tail_rec*>(tails);
+    a.counter = static_cast<unsigned long long*>(counter);
+    a.cap = 1;
+    float ms_min = 0.f;
+    for (int r = 0; r < 4 && st == BFS_OK; ++r) {
+      if (hipEventRecord(e0, s) != hipSuccess || sp.ks->corr(false, TUNE_SEGS, s, a) != hipSuccess ||
+          hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+        st = BFS_ERR_HIP;
+        break;
+      }
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = BFS_ERR_HIP;
+      if (r == 1 || (r > 1 && ms < ms_min)) ms_min = ms;
+    }
+    sp.tile_us[i] = ms_min * 1000.f / float(Kt * TUNE_SEGS);
+    if (i == 0 || ms_min < best_tile_ms) {
+      sp.tile = TILES[i];
+      best_tile_ms = ms_min;
+    }
   }
   if (y) (void)hipFree(y);
   if (tails) (void)hipFree(tails);
@@ -805,6 +858,7 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.tw1 = g.sp->tw1;
     c.tw2 = g.sp->tw2;
     c.K = p->K;
+    c.tile = g.sp->tile;
     c.kappa = p->kappa;
     c.sigma = dense ? sigma : b->sigma;
     c.tails = b->tails;
@@ -914,6 +968,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     sp.cand = (d->candidate && int(d->candidate) <= c.count) ? int(d->candidate) - 1 : 0;
     sp.ks = c.ks[sp.cand];
     sp.n_cand = c.count;
+    sp.tile = d->tile ? d->tile : default_tile(*sp.ks);
     sp.bank_bytes = uint64_t(p->K) * sp.M * sp.ks->spec_size;
     for (int i = 0; i < c.count; ++i)
       sp.tab_bytes = std::max<uint64_t>(sp.tab_bytes, table_elems(*c.ks[i]) * c.ks[i]->real_size);
@@ -950,7 +1005,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     if (st != BFS_OK) break;
   }
   if (st == BFS_OK) st = build_banks(p, d);
-  if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate)
+  if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate && !d->tile)
     for (SizePlan& sp : p->sizes)
       if (st == BFS_OK) st = tune_size(p, sp);
   if (st != BFS_OK) {
@@ -989,6 +1044,8 @@ bfs_status bfsearch_plan_kernel_info(const bfs_plan* p, uint32_t n, bfs_kernel_i
   out->candidate = uint32_t(sp->cand);
   out->n_candidates = uint32_t(sp->n_cand);
   for (int i = 0; i < MAX_CANDIDATES && i < 8; ++i) out->tuned_us[i] = sp->tuned_us[i];
+  out->tile = sp->tile;
+  for (int i = 0; i < N_TILES; ++i) out->tile_us[i] = sp->tile_us[i];
   return BFS_OK;
 }
 

@@ -88,6 +88,7 @@ def _desc(bfs, **kw):
     ("n_min", 2048),        # shorter than the 4096-sample templates
     ("flags", 4),           # unknown flag
     ("candidate", 99),      # no such kernel candidate
+    ("tile", 1 << 20),      # tile beyond the segment limit
 ])
 def test_plan_rejects_invalid_descriptor(bfs, field, value):
     d, keep = _desc(bfs, **{field: value})
@@ -102,8 +103,9 @@ def test_plan_desc_layout_matches_header(bfs):
     off = {f: getattr(bfs.PlanDesc, f).offset for f, _ in bfs.PlanDesc._fields_}
     assert off["n"] == 0 and off["n_min"] == 4 and off["fs"] == 8
     assert off["flags"] == off["device"] + 4 and off["candidate"] == off["flags"] + 4
+    assert off["tile"] == off["candidate"] + 4
     assert ctypes.sizeof(bfs.PlanDesc) % 8 == 0
-    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4
+    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4
 
 
 def test_plan_rejects_template_longer_than_segment(bfs):

@@ -425,6 +425,8 @@ def test_autotuned_plan_reports_timings_and_stays_correct(bfs):
             print("autotuned", info)
             assert len(info["tuned_us"]) == info["n_candidates"] and all(t > 0 for t in info["tuned_us"])
             assert info["tuned_us"][info["candidate"]] == min(info["tuned_us"])
+            assert all(v > 0 for v in info["tile_us"].values())
+            assert info["tile_us"][info["tile"]] == min(info["tile_us"].values())
 
 
 @pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"])
@@ -450,3 +452,27 @@ def test_c3_full_dense_bank_16bit_against_oracle_subset(bfs, prec):
     common, band = compare_tails(sub, out["tails"], out["sigma"], w.kappa, TOL[prec],
                                  lambda s, j: oracle.correlate_fft(y.astype(np.float64), temps[j]), floor)
     print(f"C3 {prec}: {total} tails over 2^20 templates; subset common {common}, band-only {band}")
+
+
+def test_workgroup_order_tiles_cover_every_correlation_once(bfs):
+    # the XCD-aware order maps a 1-D grid onto (template, segment) pairs; K = 13 (not a
+    # multiple of 8) and S = 7 (not a multiple of most tiles): every tile gives the same
+    # sigma and tails as tile 1, bitwise, and those match the oracle
+    n = 2048
+    rng = np.random.default_rng(14)
+    ys = rng.standard_normal((7, n)).astype(np.float32)
+    temps = rng.standard_normal((13, 300))
+    kappa = 3.0
+    res = {}
+    for t in (1, 2, 3, 4, 7, 16):
+        with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32", tile=t) as plan:
+            assert plan.kernel_info()["tile"] == t
+            with plan.filter(_dev(ys, np.float32)) as job:
+                res[t] = (job.fetch_tails()[0], job.fetch_sigma())
+    for t, (tl, sg) in res.items():
+        assert np.array_equal(tl, res[1][0]) and np.array_equal(sg, res[1][1]), t
+    tw = [x.astype(np.float32).astype(np.float64) for x in temps]
+    out = oracle.search([y.astype(np.float64) for y in ys], tw, kappa)
+    assert np.all(res[1][1] > 0) and np.max(np.abs(res[1][1] - out["sigma"]) / out["sigma"]) <= TOL["f32"]
+    compare_tails(res[1][0], out["tails"], out["sigma"], kappa, TOL["f32"],
+                  lambda s, j: oracle.correlate_fft(ys[s].astype(np.float64), tw[j]))
