@@ -460,8 +460,10 @@ __device__ __forceinline__ bool tile_map(uint32_t b, uint32_t K, uint32_t S, uin
     jj = rem / r;
     s = full * T + (rem - jj * r);
   }
-  j = 8u * jj + x;
-  row = s;
+  // the quotients above come out of VALU division code; readfirstlane marks
+  // them wave-uniform so the buffer resources built from them stay scalar
+  j = __builtin_amdgcn_readfirstlane(8u * jj + x);
+  row = __builtin_amdgcn_readfirstlane(s);
   return true;
 }
 
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
-  const uint32_t s = seg_ids ? seg_ids[row] : row;
+  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row);
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   cx<T> v[F::P];
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
-  const uint32_t s = seg_ids ? seg_ids[row] : row;
+  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row);
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   cx<T> v[F::P];
