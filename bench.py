@@ -36,7 +36,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
 # for the kernel sources they were taken on (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "77e6e2cec26f377f": {"f32": 2.1999e9, "f32-w16f": 1.0908e9},
+    "e0fcacb034c7d33b": {"f32": 2.2146e9, "f32-w16f": 1.0938e9},
 }
 
 
@@ -106,9 +106,11 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2):
 
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
     t0 = time.perf_counter()
-    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision, tail_capacity=1 << 22)
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision, tail_capacity=1 << 22,
+                    autotune=True)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    kernel = plan.kernel_info()
     corr_ms, job_ms, lat_ms, n_tails = [], [], [], 0
 
     def finish(item):
@@ -139,7 +141,7 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     info = {"bank_bytes": plan.bank_bytes, "threads": plan.threads_per_correlation,
-            "job_device_ms": float(sum(job_ms) / len(job_ms))}
+            "job_device_ms": float(sum(job_ms) / len(job_ms)), "kernel": kernel}
     plan.close()
     return wall, build_s, corr_ms, lat_ms, n_tails, info
 
@@ -329,7 +331,8 @@ def main():
         "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
                        "max": float(np.max(lat_ms))},
         "job_device_ms": info["job_device_ms"],
-        "bank_build_s": build_s,
+        "kernel": info["kernel"],
+        "bank_build_and_tune_s": build_s,
         "bank_bytes": info["bank_bytes"],
         "tails_per_step": n_tails,
     }

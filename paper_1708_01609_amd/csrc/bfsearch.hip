@@ -222,6 +222,7 @@ Candidates candidates_t(uint32_t m) {
       break;
     case 32768:
       if constexpr (F32) {
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 8>();
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 4>();
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 2>();
       }
@@ -230,6 +231,7 @@ Candidates candidates_t(uint32_t m) {
       if constexpr (F32) {
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 4>();
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 2>();
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 8>();
       }
       break;
     default:
