@@ -16,7 +16,9 @@ from .bfsearch_oracle import (
     sigma_eq7,
     threshold_tails,
     search,
+    max_projection,
     TAIL_DTYPE,
+    PEAK_DTYPE,
 )
 
 __all__ = [
@@ -31,5 +33,7 @@ __all__ = [
     "sigma_eq7",
     "threshold_tails",
     "search",
+    "max_projection",
     "TAIL_DTYPE",
+    "PEAK_DTYPE",
 ]

@@ -25,6 +25,12 @@ What it computes, per segment y (length N) and template w (length L <= N):
 * tails: every (segment, template, lag) with |rho| > kappa * sigma, Eq. (9)
   applied to the absolute value as the text after it says; strict '>'.
   This is the "gather all hits" mode of Sec. 3.3 (no max selection).
+* the per-lag max projection of Sec. 3.3 (Eqs. 13-17): over all templates,
+  for every (segment, lag) that carries a tail, the tail of largest
+  significance |rho| / sigma (the quantity the threshold compares), reported
+  as the signed rho / sigma with its template.  The paper's update of the
+  projection array is racy (its text says so); here equal significances go to
+  the lowest template id, so the result is unique (see max_projection).
 
 Templates (Sec. 2 uses chirps from a spin-down model that the paper does not
 give; linear chirps stand in): w[m] = h[m] cos(2 pi (f0 t + fdot t^2 / 2)),
@@ -39,6 +45,7 @@ import numpy as np
 import scipy.fft as sfft
 
 TAIL_DTYPE = np.dtype([("segment", np.uint32), ("template", np.uint32), ("lag", np.uint32), ("rho", np.float64)])
+PEAK_DTYPE = np.dtype([("segment", np.uint32), ("lag", np.uint32), ("template", np.uint32), ("snr", np.float64)])
 
 
 def _workers() -> int:
@@ -210,4 +217,29 @@ def search(segments, templates, kappa: float, keep_rho: bool = False, chunk: int
     out = {"sigma": sig, "sigma_f": sig_f, "tails": tails}
     if keep_rho:
         out["rho"] = rhos
+    return out
+
+
+def max_projection(tails: np.ndarray, sigma: np.ndarray) -> np.ndarray:
+    """Per-lag max projection of a tail list (Sec. 3.3, Eqs. 13-17).
+
+    tails: TAIL_DTYPE records; sigma: [S, K] sigma of every correlation.  For each
+    (segment, lag) present in `tails`, keep the tail with the largest |rho| / sigma;
+    ties go to the lowest template id.  Returns PEAK_DTYPE records sorted by
+    (segment, lag), with snr = rho / sigma of the kept tail (sign of rho kept).
+    """
+    best: dict = {}
+    for s, j, n, r in zip(tails["segment"], tails["template"], tails["lag"], tails["rho"]):
+        s, j, n, r = int(s), int(j), int(n), float(r)
+        v = abs(r) / float(sigma[s, j])
+        key = (s, n)
+        if key not in best:
+            best[key] = (v, j, r)
+            continue
+        bv, bj, _ = best[key]
+        if v > bv or (v == bv and j < bj):
+            best[key] = (v, j, r)
+    out = np.zeros(len(best), dtype=PEAK_DTYPE)
+    for i, ((s, n), (v, j, r)) in enumerate(sorted(best.items())):
+        out[i] = (s, n, j, r / float(sigma[s, j]))
     return out

@@ -382,7 +382,6 @@ struct Group {
   const SizePlan* sp = nullptr;
   uint32_t count = 0;
   uint64_t y_off = 0;     // byte offset of the group's spectra in the job's y buffer
-  uint64_t y_spec = 0;    // byte offset of the group's first segment in job_spectra's output (doubles)
   uint32_t first = 0;     // index of the group's first entry in the segment table
 };
 
@@ -767,17 +766,14 @@ struct Layout {
   JobNeed need;
 };
 
-bfs_status make_layout(const bfs_plan* p, const void* y_dev, const uint64_t* offs, const uint32_t* lens,
-                       uint32_t S, Layout& L) {
+bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layout& L) {
   L.seg_len.resize(S);
   for (uint32_t s = 0; s < S; ++s) {
     const uint32_t n = lens ? lens[s] : p->n_max;
     if (!size_plan(p, n)) return BFS_ERR_INVALID_ARG;
     L.seg_len[s] = n;
   }
-  (void)y_dev;
-  (void)offs;
-  uint64_t ybytes = 0, zbytes = 0, spec = 0, first = 0;
+  uint64_t ybytes = 0, zbytes = 0, first = 0;
   for (int i = int(p->sizes.size()) - 1; i >= 0; --i) {
     const SizePlan& sp = p->sizes[size_t(i)];
     uint32_t cnt = 0;
@@ -794,8 +790,6 @@ bfs_status make_layout(const bfs_plan* p, const void* y_dev, const uint64_t* off
     first += cnt;
     L.groups.push_back(g);
   }
-  // job_spectra output offsets follow global segment order
-  (void)spec;
   L.need.ybytes = ybytes;
   L.need.zbytes = zbytes;
   L.need.sigma = uint64_t(S) * p->K;
@@ -1057,7 +1051,7 @@ bfs_status bfsearch_filter(bfs_plan* p, const void* y_dev, const uint64_t* seg_o
   *out = nullptr;
   if (!p || !y_dev || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
   Layout L;
-  bfs_status rs = make_layout(p, y_dev, seg_offsets, seg_lengths, S, L);
+  bfs_status rs = make_layout(p, seg_lengths, S, L);
   if (rs != BFS_OK) return rs;
   auto* j = new (std::nothrow) bfs_job();
   if (!j) return BFS_ERR_OUT_OF_MEMORY;
@@ -1166,7 +1160,7 @@ bfs_status bfsearch_job_poll(bfs_job* j, int* done) {
 bfs_status bfsearch_plan_job_bytes(const bfs_plan* p, const uint32_t* seg_lengths, uint32_t S, uint64_t* bytes) {
   if (!p || !bytes || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
   Layout L;
-  const bfs_status rs = make_layout(p, nullptr, nullptr, seg_lengths, S, L);
+  const bfs_status rs = make_layout(p, seg_lengths, S, L);
   if (rs != BFS_OK) return rs;
   *bytes = L.need.ybytes + L.need.zbytes + L.need.sigma * sizeof(double) + p->cap * sizeof(tail_rec) + L.need.meta +
            256;
@@ -1201,7 +1195,7 @@ bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg
   if (!size_plan(p, seg_len)) return BFS_ERR_INVALID_ARG;
   std::vector<uint32_t> lens(S, seg_len);
   Layout L;
-  bfs_status rs = make_layout(p, y_dev, nullptr, lens.data(), S, L);
+  bfs_status rs = make_layout(p, lens.data(), S, L);
   if (rs != BFS_OK) return rs;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);

@@ -32,6 +32,9 @@ MUTANTS = {
                         "return f0s[j % int(n_f0)], fds[j // int(n_f0)]"),
     "no_normalisation": ("w = w / np.sqrt(e)", "w = w / e"),
     "direct_lag_reversed": ("rho += w[m] * np.roll(y, -m)", "rho += w[m] * np.roll(y, m)"),
+    "projection_raw_rho": ("v = abs(r) / float(sigma[s, j])", "v = abs(r)"),
+    "projection_signed": ("v = abs(r) / float(sigma[s, j])", "v = r / float(sigma[s, j])"),
+    "projection_highest_id": ("if v > bv or (v == bv and j < bj):", "if v > bv or (v == bv and j > bj):"),
 }
 
 PIN_TESTS = [
@@ -48,6 +51,8 @@ PIN_TESTS = [
     (pins.test_threshold_strict_and_absolute, [()]),
     (pins.test_search_tails_equal_brute_force_threshold, [()]),
     (pins.test_sigma_expectation_equals_inband_template_energy, [()]),
+    (pins.test_max_projection_equals_brute_force_argmax, [()]),
+    (pins.test_max_projection_ties_scale_and_sign, [()]),
 ]
 
 

@@ -253,3 +253,50 @@ def test_c1_injection_recovered_by_raw_rho():
 
 def _noise_only(w):
     return bandlimited_noise(w.n, w.fs, seeded_rng(w.config_id, 0, 0, "noise"))
+
+
+def test_max_projection_equals_brute_force_argmax():
+    # per-lag max projection (Sec. 3.3, Eqs. 13-17) against an explicit argmax over every
+    # template's brute-force rho/sigma at each (segment, lag), lowest id first on ties
+    r = _rng(21)
+    segs = [r.standard_normal(64), r.standard_normal(32)]
+    temps = [r.standard_normal(5), r.standard_normal(12), r.standard_normal(1), r.standard_normal(7)]
+    kappa = 1.2
+    out = oracle.search(segs, temps, kappa)
+    proj = oracle.max_projection(out["tails"], out["sigma"])
+    expect = []
+    for s, y in enumerate(segs):
+        rows = []
+        for w in temps:
+            rho = _brute_force(list(y), list(w))
+            sig = math.sqrt(sum(v * v for v in rho) / len(rho))
+            rows.append((rho, sig))
+        for lag in range(len(y)):
+            best = None
+            for j, (rho, sig) in enumerate(rows):
+                v = rho[lag] / sig
+                if abs(rho[lag]) > kappa * sig and (best is None or abs(v) > abs(best[1])):
+                    best = (j, v)
+            if best is not None:
+                expect.append((s, lag, best[0], best[1]))
+    assert [(int(a), int(b), int(c)) for a, b, c, _ in proj] == [(a, b, c) for a, b, c, _ in expect]
+    np.testing.assert_allclose(proj["snr"], [e[3] for e in expect], rtol=1e-11, atol=1e-12)
+    assert len(proj) > 10
+
+
+def test_max_projection_ties_scale_and_sign():
+    r = _rng(22)
+    y = r.standard_normal(128)
+    w = r.standard_normal(9)
+    # templates 1 and 3 are w scaled by 2 and 0.5: the same rho/sigma everywhere, so every lag
+    # they win goes to template 1 (lowest id among the tied); template 0 is unrelated
+    temps = [r.standard_normal(9), 2.0 * w, r.standard_normal(4), 0.5 * w]
+    out = oracle.search([y], temps, 1.0)
+    proj = oracle.max_projection(out["tails"], out["sigma"])
+    assert 3 not in set(proj["template"].tolist()) and 1 in set(proj["template"].tolist())
+    # a single template: the projection is its tail list, with snr = rho / sigma (sign kept)
+    one = oracle.search([y], [w], 1.0)
+    p1 = oracle.max_projection(one["tails"], one["sigma"])
+    assert np.array_equal(p1["lag"], one["tails"]["lag"]) and np.all(p1["template"] == 0)
+    np.testing.assert_allclose(p1["snr"], one["tails"]["rho"] / one["sigma"][0, 0], rtol=1e-14)
+    assert np.any(p1["snr"] < 0) and np.any(p1["snr"] > 0)
