@@ -67,6 +67,10 @@ typedef enum {
                                 the first candidate; the tile whose segment
                                 spectra fill half an XCD's L2) */
 
+#define BFS_PLAN_PROJECT 4u  /* per-lag max projection (Sec. 3.3, Eqs. 13-17)
+                                instead of the tail list: see
+                                bfsearch_fetch_projection */
+
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
 
@@ -79,6 +83,17 @@ typedef struct {
   uint32_t reserved;
   double rho;
 } bfs_tail;
+
+/* One entry of the per-lag max projection (16 bytes): at lag `lag` of
+ * segment `segment`, the template with the largest |rho| / sigma among those
+ * whose |rho| exceeds kappa * sigma; snr = rho / sigma of that template, sign
+ * of rho kept (FP32).  Equal significances go to the lowest template id. */
+typedef struct {
+  uint32_t segment;
+  uint32_t lag;
+  uint32_t template_id;
+  float snr;
+} bfs_peak;
 
 /* Plan descriptor.  All pointers are host memory, read during the call only. */
 typedef struct {
@@ -182,6 +197,19 @@ bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* se
  *   written are an arbitrary subset. */
 bfs_status bfsearch_fetch_tails(bfs_job* job, bfs_tail* out_host, uint64_t capacity,
                                 uint64_t* n_written, uint64_t* n_total);
+
+/* BFS_PLAN_PROJECT plans: wait for the job and copy its per-lag max
+ * projection to out_host, sorted by (segment, lag), one entry per lag that
+ * carries at least one tail (the paper's array A reduced over templates, with
+ * the data of maximal rho per offset as in its host array B, Sec. 3.3).  The
+ * kernels raise each lag's entry with a 64-bit atomicMax of
+ * (significance bits, lowest template id, sign), so the result is the same
+ * whatever the order of the updates.  *n_total = entries found; returns
+ * BFS_ERR_TAIL_OVERFLOW when it exceeds capacity (the first `capacity` in
+ * order are written).  BFS_ERR_INVALID_ARG for plans without the flag;
+ * bfsearch_fetch_tails likewise refuses projection plans. */
+bfs_status bfsearch_fetch_projection(bfs_job* job, bfs_peak* out_host, uint64_t capacity,
+                                     uint64_t* n_written, uint64_t* n_total);
 
 /* Wait for the job and copy sigma[s][j] (FP64, Eq. 6 by Parseval) to out_host
  * ([n_segments][K] doubles). */

@@ -26,11 +26,13 @@ BFS_ERR_UNSUPPORTED = -5
 FP64, FP32, FP32_W16F, FP32_W16B = 0, 1, 2, 3
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
+PLAN_PROJECT = 4
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
 TAIL_DTYPE = np.dtype(
     [("segment", "<u4"), ("template", "<u4"), ("lag", "<u4"), ("reserved", "<u4"), ("rho", "<f8")]
 )
+PEAK_DTYPE = np.dtype([("segment", "<u4"), ("lag", "<u4"), ("template", "<u4"), ("snr", "<f4")])
 
 
 class PlanDesc(ctypes.Structure):
@@ -101,6 +103,7 @@ def _load() -> ctypes.CDLL:
         "bfsearch_filter": [vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)],
         "bfsearch_fetch_tails": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_sigma": [vp, vp],
+        "bfsearch_fetch_projection": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_job_timing": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "bfsearch_job_release": [vp],
         "bfsearch_job_poll": [vp, ctypes.POINTER(ctypes.c_int)],
@@ -162,13 +165,13 @@ class Plan:
                  templates: np.ndarray | None = None, precision: str = "f32",
                  tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
                  n_min: int | None = None, graph: bool = False, autotune: bool = False,
-                 candidate: int = 0, tile: int = 0):
+                 candidate: int = 0, tile: int = 0, project: bool = False):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
         d.n_min = int(n_min) if n_min else 0
         d.precision = PRECISIONS[precision]
         d.tail_capacity, d.hbm_budget_bytes, d.device = int(tail_capacity), int(hbm_budget_bytes), int(device)
-        d.flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0)
+        d.flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0) | (PLAN_PROJECT if project else 0)
         d.candidate = int(candidate)
         d.tile = int(tile)
         keep = []
@@ -336,6 +339,18 @@ class Job:
         if st == BFS_ERR_TAIL_OVERFLOW and allow_overflow:
             return out[: nw.value], nt.value
         _check(st, "bfsearch_fetch_tails")
+        return out[: nw.value], nt.value
+
+    def fetch_projection(self, capacity: int | None = None, allow_overflow: bool = False):
+        """Per-lag max projection (projection plans): PEAK_DTYPE records sorted by (segment, lag), one
+        per lag carrying a tail, and the exact number of such lags."""
+        cap = sum(self.lengths) if capacity is None else int(capacity)
+        out = np.zeros(cap, dtype=PEAK_DTYPE)
+        nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
+        st = _lib.bfsearch_fetch_projection(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw),
+                                            ctypes.byref(nt))
+        if not (st == BFS_ERR_TAIL_OVERFLOW and allow_overflow):
+            _check(st, "bfsearch_fetch_projection")
         return out[: nw.value], nt.value
 
     def done(self) -> bool:

@@ -396,10 +396,17 @@ __device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, cons
 // Stage 3, threshold: keep |z| > thr (thr = kappa sqrt(S) in z units) with
 // one ballot per value and one atomicAdd per wave and value; records past
 // cap are counted but not written.  any: this thread may hold a tail.
+// With prow set (per-lag max projection) a tail is not written to the list:
+// it raises prow[lag] with atomicMax to the key
+//   (float bits of |rho| / sigma) << 32 | (0x7fffffff - j) << 1 | (rho < 0),
+// so the largest significance wins, equal significances go to the lowest
+// template id, and the result does not depend on the order of the updates.
+// rootS = sqrt(S) = N sigma, so |rho| / sigma = |z| / rootS.
 template <class F, typename T, class Z>
 __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool any, uint32_t s, uint32_t j,
                                            double N, tail_rec* __restrict__ tails,
-                                           unsigned long long* __restrict__ counter, uint64_t cap, int t) {
+                                           unsigned long long* __restrict__ counter, uint64_t cap,
+                                           unsigned long long* __restrict__ prow, double rootS, int t) {
   const int lane = t & 63;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
@@ -419,18 +426,56 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool an
           if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
           base = __shfl(base, leader, 64);
           if (pred) {
-            const uint64_t idx = base + __popcll(mask & below);
-            if (idx < cap) {
-              tail_rec r;
-              r.segment = s;
-              r.template_id = j;
-              r.lag = 2 * n + uint32_t(h);
-              r.reserved = 0;
-              r.rho = double(val) / N;
-              tails[idx] = r;
+            const uint32_t lag = 2 * n + uint32_t(h);
+            if (prow) {
+              const float snr = float(fabs(double(val)) / rootS);
+              const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(snr)) << 32) |
+                                             (static_cast<unsigned long long>(0x7fffffffu - j) << 1) |
+                                             (val < T(0) ? 1ull : 0ull);
+              atomicMax(prow + lag, key);
+            } else {
+              const uint64_t idx = base + __popcll(mask & below);
+              if (idx < cap) {
+                tail_rec r;
+                r.segment = s;
+                r.template_id = j;
+                r.lag = lag;
+                r.reserved = 0;
+                r.rho = double(val) / N;
+                tails[idx] = r;
+              }
             }
           }
         }
+      }
+    }
+  }
+}
+
+// Projection keys -> list of (index, key) for every nonzero key (order
+// arbitrary; the host sorts), one atomicAdd per wave.  Entries past cap are
+// counted but not written.
+__global__ __launch_bounds__(256) void project_compact_kernel(const unsigned long long* __restrict__ keys, uint64_t n,
+                                                              unsigned long long* __restrict__ list,
+                                                              unsigned long long* __restrict__ counter, uint64_t cap) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  for (uint64_t base_i = uint64_t(blockIdx.x) * blockDim.x; base_i < n; base_i += stride) {
+    const uint64_t i = base_i + threadIdx.x;
+    const unsigned long long key = i < n ? keys[i] : 0ull;
+    const bool pred = key != 0ull;
+    const uint64_t mask = __ballot(pred);
+    if (!mask) continue;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (pred) {
+      const uint64_t idx = base + __popcll(mask & below);
+      if (idx < cap) {
+        list[2 * idx] = i;
+        list[2 * idx + 1] = key;
       }
     }
   }
@@ -470,7 +515,8 @@ __device__ __forceinline__ bool tile_map(uint32_t b, uint32_t K, uint32_t S, uin
 // One workgroup per (template j, spectrum row), in the order of tile_map over
 // a 1-D grid of 8 ceil(K/8) n_rows workgroups.
 //   bank  [K][M] packed template spectra (storage TW), yspec [n_rows][M] packed;
-//   row r is segment seg_ids[r] (or r), the id used for sigma and tails.
+//   row r is segment seg_ids[r] (or r), the id used for sigma and tails;
+//   proj (may be null): projection keys, row r's N lags at proj + proj_off[r].
 //   tw_u  exp(+2 pi i k / N), tw1/tw2 the FFT twiddles (see bfs_fft3.h).
 // z = IDFT_M(Z) gives z_n = N (rho_{2n} + i rho_{2n+1}); with
 // S = |C_0|^2 + |C_M|^2 + 2 sum_{k=1}^{M-1} |C_k|^2 (FP64), sigma = sqrt(S)/N and
@@ -481,7 +527,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
-    T* __restrict__ rho_dense) {
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, T* __restrict__ rho_dense) {
   constexpr int M = F::M;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -511,7 +557,10 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
 #pragma unroll
     for (int i = 0; i < F::P; ++i) mx = fmax(mx, fmax(fabs(v[i].x), fabs(v[i].y)));
     const bool any = (mx > thr) && (rootS > 0.0);
-    if (__ballot(any)) emit_tails<F, T>(z, 0u, thr, any, s, j, N, tails, counter, cap, t);
+    if (__ballot(any)) {
+      unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
+      emit_tails<F, T>(z, 0u, thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
+    }
   }
 }
 
@@ -528,7 +577,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
-    T* __restrict__ rho_dense) {
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, T* __restrict__ rho_dense) {
   constexpr int H = F::M, M = 2 * H;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -590,8 +639,9 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     }
     const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
-      emit_tails<F, T>(z_lo, 0u, thr, any, s, j, N, tails, counter, cap, t);
-      emit_tails<F, T>(z_hi, uint32_t(H), thr, any, s, j, N, tails, counter, cap, t);
+      unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
+      emit_tails<F, T>(z_lo, 0u, thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z_hi, uint32_t(H), thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
     }
   }
 }

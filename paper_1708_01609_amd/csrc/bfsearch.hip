@@ -61,6 +61,8 @@ struct CorrArgs {
   tail_rec* tails;
   unsigned long long* counter;
   uint64_t cap;
+  unsigned long long* proj;  // projection keys (null: tail list)
+  const uint64_t* proj_off;  // per grid row: offset of its lags in proj
   void* rho;
 };
 
@@ -124,10 +126,10 @@ struct Impl {
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
     if constexpr (SPLIT)
       hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, rho);
     else
       hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, rho);
   }
   // 1-D grid in the XCD-aware order of tile_map: 8 ceil(K/8) S workgroups
   static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
@@ -319,6 +321,7 @@ struct JobNeed {
   uint64_t zbytes = 0;     // transform scratch of the split group (0 if none)
   uint64_t sigma = 0;      // S * K doubles
   uint64_t meta = 0;       // segment table bytes
+  uint64_t proj = 0;       // projection entries (sum of segment lengths; 0: tail list)
 };
 
 struct JobBuffers {
@@ -330,7 +333,9 @@ struct JobBuffers {
   unsigned long long* counter = nullptr;
   void* meta = nullptr;       // device segment table
   void* meta_host = nullptr;  // pinned host staging of the table
-  unsigned long long* count_host = nullptr;  // pinned copy of the tail counter, written by the job
+  unsigned long long* proj = nullptr;        // projection keys [sum of segment lengths]
+  unsigned long long* plist = nullptr;       // compacted (index, key) pairs
+  unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
   bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
   uint64_t tails_host_cap = 0;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -366,6 +371,7 @@ struct bfs_plan {
   std::vector<SizePlan> sizes;  // ascending N: sizes[i].N = n_min << i
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
   bool graph = false;
+  bool project = false;  // per-lag max projection instead of the tail list
   hipStream_t copy_stream = nullptr;
   hipStream_t capture_stream = nullptr;
   std::mutex capture_mu;  // one capture at a time on capture_stream
@@ -416,7 +422,7 @@ bfs_status alloc_checked(void** p, uint64_t bytes) {
 void free_job_buffers(JobBuffers* b) {
   if (!b) return;
   for (void* q : {b->y, b->z, static_cast<void*>(b->sigma), static_cast<void*>(b->tails),
-                  static_cast<void*>(b->counter), b->meta})
+                  static_cast<void*>(b->counter), b->meta, static_cast<void*>(b->proj), static_cast<void*>(b->plist)})
     if (q) (void)hipFree(q);
   if (b->meta_host) (void)hipHostFree(b->meta_host);
   if (b->count_host) (void)hipHostFree(b->count_host);
@@ -452,7 +458,7 @@ bfs_status validate(const bfs_plan_desc* d) {
   if (d->tail_capacity < 1) return BFS_ERR_INVALID_ARG;
   if (d->precision < BFS_FP64 || d->precision > BFS_FP32_W16B) return BFS_ERR_INVALID_ARG;
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
-  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE)) return BFS_ERR_INVALID_ARG;
+  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT)) return BFS_ERR_INVALID_ARG;
   if (d->candidate > uint32_t(MAX_CANDIDATES)) return BFS_ERR_INVALID_ARG;
   if (d->tile > 65535) return BFS_ERR_INVALID_ARG;
   if (d->explicit_templates) {
@@ -688,7 +694,11 @@ bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
 }
 
 bool covers(const JobNeed& c, const JobNeed& n) {
-  return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta;
+  return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta && c.proj >= n.proj;
+}
+
+uint64_t need_bytes(const JobNeed& c, uint64_t cap) {
+  return c.ybytes + c.zbytes + c.sigma * sizeof(double) + cap * sizeof(tail_rec) + c.meta + 3 * 8 * c.proj + 256;
 }
 
 bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
@@ -708,12 +718,12 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
     c.zbytes = std::max(c.zbytes, b->cap.zbytes);
     c.sigma = std::max(c.sigma, b->cap.sigma);
     c.meta = std::max(c.meta, b->cap.meta);
+    c.proj = std::max(c.proj, b->cap.proj);
   }
-  const uint64_t tbytes = p->cap * sizeof(tail_rec);
-  uint64_t bytes = c.ybytes + c.zbytes + c.sigma * sizeof(double) + tbytes + c.meta + 256;
+  uint64_t bytes = need_bytes(c, p->cap);
   if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) {
     c = need;  // the minimal set, after dropping the pool
-    bytes = c.ybytes + c.zbytes + c.sigma * sizeof(double) + tbytes + c.meta + 256;
+    bytes = need_bytes(c, p->cap);
   }
   for (auto* b : p->pool) free_job_buffers(b);
   p->pool.clear();
@@ -725,9 +735,11 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   bfs_status st = alloc_checked(&b->y, c.ybytes);
   if (st == BFS_OK && c.zbytes) st = alloc_checked(&b->z, c.zbytes);
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->sigma), c.sigma * sizeof(double));
-  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->tails), tbytes);
+  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->tails), p->cap * sizeof(tail_rec));
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->counter), 256);
   if (st == BFS_OK) st = alloc_checked(&b->meta, c.meta);
+  if (st == BFS_OK && c.proj) st = alloc_checked(reinterpret_cast<void**>(&b->proj), c.proj * 8);
+  if (st == BFS_OK && c.proj) st = alloc_checked(reinterpret_cast<void**>(&b->plist), c.proj * 16);
   if (st == BFS_OK && (hipHostMalloc(&b->meta_host, c.meta ? c.meta : 256, hipHostMallocDefault) != hipSuccess ||
                        hipHostMalloc(reinterpret_cast<void**>(&b->count_host), 256, hipHostMallocDefault) !=
                            hipSuccess)) {
@@ -793,20 +805,26 @@ bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layo
   L.need.ybytes = ybytes;
   L.need.zbytes = zbytes;
   L.need.sigma = uint64_t(S) * p->K;
-  L.need.meta = uint64_t(S) * (sizeof(uint64_t) + sizeof(uint32_t)) + 256;
+  L.need.meta = uint64_t(S) * (2 * sizeof(uint64_t) + sizeof(uint32_t)) + 256;
+  if (p->project)
+    for (uint32_t s = 0; s < S; ++s) L.need.proj += L.seg_len[s];
   return BFS_OK;
 }
 
-// Fill the pinned segment table: [S] device addresses in group order, then [S] global ids.
+// Fill the pinned segment table, per entry in group order: [S] device address
+// of the samples, [S] offset of the segment's lags in the projection keys
+// (segments back to back in the caller's order), [S] caller index.
 void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, const Layout& L, void* host) {
   const uint32_t S = uint32_t(L.seg_len.size());
   auto* ptrs = static_cast<uint64_t*>(host);
-  auto* ids = reinterpret_cast<uint32_t*>(ptrs + S);
+  auto* poff = ptrs + S;
+  auto* ids = reinterpret_cast<uint32_t*>(poff + S);
   const size_t rs = p->sizes[0].ks->real_size;
-  std::vector<uint64_t> off(S);
+  std::vector<uint64_t> off(S), lag0(S);
   uint64_t acc = 0;
   for (uint32_t s = 0; s < S; ++s) {
     off[s] = offs ? offs[s] : acc;
+    lag0[s] = acc;
     acc += L.seg_len[s];
   }
   for (const Group& g : L.groups) {
@@ -814,6 +832,7 @@ void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, con
     for (uint32_t s = 0; s < S; ++s) {
       if (L.seg_len[s] != g.sp->N) continue;
       ptrs[k] = uint64_t(reinterpret_cast<uintptr_t>(y_dev)) + off[s] * rs;
+      poff[k] = lag0[s];
       ids[k] = s;
       ++k;
     }
@@ -826,12 +845,19 @@ void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, con
 bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
                         hipStream_t st, bool with_events) {
   const uint32_t S = uint32_t(L.seg_len.size());
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(1), 0ull);
+  const bool project = p->project && !dense;
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(2), 0ull);
   HIP_TRY(hipGetLastError());
-  const uint64_t tbytes = uint64_t(S) * (sizeof(uint64_t) + sizeof(uint32_t));
+  if (project) {
+    const uint64_t n = L.need.proj;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, b->proj, n, 0ull);
+    HIP_TRY(hipGetLastError());
+  }
+  const uint64_t tbytes = uint64_t(S) * (2 * sizeof(uint64_t) + sizeof(uint32_t));
   HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, tbytes, hipMemcpyHostToDevice, st));
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
-  const auto* dids = reinterpret_cast<const uint32_t*>(dptr + S);
+  const auto* dpoff = dptr + S;
+  const auto* dids = reinterpret_cast<const uint32_t*>(dpoff + S);
   char* ybase = static_cast<char*>(b->y);
   for (const Group& g : L.groups) {
     const KernelSet& ks = *g.sp->ks;
@@ -860,12 +886,21 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.tails = b->tails;
     c.counter = b->counter;
     c.cap = dense ? 0 : p->cap;
+    c.proj = project ? b->proj : nullptr;
+    c.proj_off = project ? dpoff + g.first : nullptr;
     c.rho = rho;
     HIP_TRY(g.sp->ks->corr(dense, g.count, st, c));
   }
   if (with_events) HIP_TRY(hipEventRecord(b->ev[2], st));
-  // the tail count travels with the job, so a fetch needs one copy only
-  HIP_TRY(hipMemcpyAsync(b->count_host, b->counter, sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  if (project) {
+    const uint64_t n = L.need.proj;
+    const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(project_compact_kernel, dim3(blocks), dim3(256), 0, st, b->proj, n, b->plist, b->counter + 1,
+                       n);
+    HIP_TRY(hipGetLastError());
+  }
+  // the counts travel with the job, so a fetch needs one copy only
+  HIP_TRY(hipMemcpyAsync(b->count_host, b->counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
   return BFS_OK;
 }
 
@@ -988,6 +1023,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     return BFS_ERR_OUT_OF_MEMORY;
   }
   p->graph = (d->flags & BFS_PLAN_GRAPH) != 0;
+  p->project = (d->flags & BFS_PLAN_PROJECT) != 0;
   if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
       hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
     free_plan(p);
@@ -1088,6 +1124,7 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
                                 uint64_t* n_total) {
   if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
   bfs_plan* p = j->plan;
+  if (p->project) return BFS_ERR_INVALID_ARG;
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(hipEventSynchronize(b->ev[3]));
@@ -1118,6 +1155,48 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
   });
   const uint64_t nw = std::min<uint64_t>(on_dev, capacity);
   if (nw) std::memcpy(out_host, tmp, nw * sizeof(bfs_tail));
+  *n_written = nw;
+  *n_total = count;
+  return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
+}
+
+bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t capacity, uint64_t* n_written,
+                                     uint64_t* n_total) {
+  if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
+  bfs_plan* p = j->plan;
+  if (!p->project) return BFS_ERR_INVALID_ARG;
+  JobBuffers* b = j->buf;
+  if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
+  HIP_TRY(hipEventSynchronize(b->ev[3]));
+  const unsigned long long count = b->count_host[1];  // <= the number of lags, the list's size
+  std::vector<unsigned long long> list(2 * count);
+  if (count) {
+    HIP_TRY(hipMemcpyAsync(list.data(), b->plist, 2 * count * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           p->copy_stream));
+    HIP_TRY(hipStreamSynchronize(p->copy_stream));
+  }
+  // global lag index -> (segment, lag): segments back to back in the caller's order
+  std::vector<uint64_t> lag0(j->S + 1, 0);
+  for (uint32_t s = 0; s < j->S; ++s) lag0[s + 1] = lag0[s] + j->seg_len[s];
+  std::vector<bfs_peak> peaks(count);
+  for (uint64_t i = 0; i < count; ++i) {
+    const uint64_t idx = list[2 * i];
+    const unsigned long long key = list[2 * i + 1];
+    const uint32_t s = uint32_t(std::upper_bound(lag0.begin(), lag0.end(), idx) - lag0.begin() - 1);
+    const uint32_t lo = uint32_t(key & 0xffffffffull);
+    const uint32_t bits = uint32_t(key >> 32);
+    float snr;
+    std::memcpy(&snr, &bits, sizeof(snr));
+    peaks[i].segment = s;
+    peaks[i].lag = uint32_t(idx - lag0[s]);
+    peaks[i].template_id = 0x7fffffffu - (lo >> 1);
+    peaks[i].snr = (lo & 1u) ? -snr : snr;
+  }
+  std::sort(peaks.begin(), peaks.end(), [](const bfs_peak& a, const bfs_peak& c) {
+    return a.segment != c.segment ? a.segment < c.segment : a.lag < c.lag;
+  });
+  const uint64_t nw = std::min<uint64_t>(count, capacity);
+  if (nw) std::memcpy(out_host, peaks.data(), nw * sizeof(bfs_peak));
   *n_written = nw;
   *n_total = count;
   return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
@@ -1162,8 +1241,7 @@ bfs_status bfsearch_plan_job_bytes(const bfs_plan* p, const uint32_t* seg_length
   Layout L;
   const bfs_status rs = make_layout(p, seg_lengths, S, L);
   if (rs != BFS_OK) return rs;
-  *bytes = L.need.ybytes + L.need.zbytes + L.need.sigma * sizeof(double) + p->cap * sizeof(tail_rec) + L.need.meta +
-           256;
+  *bytes = need_bytes(L.need, p->cap);
   return BFS_OK;
 }
 

@@ -47,6 +47,7 @@ def test_library_exports_every_declared_symbol(bfs):
 def test_struct_layouts_match_header(bfs):
     assert ctypes.sizeof(bfs.PlanInfo) == 40
     assert bfs.TAIL_DTYPE.itemsize == 24
+    assert bfs.PEAK_DTYPE.itemsize == 16
     # bfs_plan_desc field order as declared (spot-check offsets of the 64-bit fields)
     assert bfs.PlanDesc.fs.offset == 8
     assert bfs.PlanDesc.tail_capacity.offset % 8 == 0
@@ -86,7 +87,7 @@ def _desc(bfs, **kw):
     ("n_min", 3000),        # not a power of two
     ("n_min", 1 << 17),     # above n
     ("n_min", 2048),        # shorter than the 4096-sample templates
-    ("flags", 4),           # unknown flag
+    ("flags", 8),           # unknown flag
     ("candidate", 99),      # no such kernel candidate
     ("tile", 1 << 20),      # tile beyond the segment limit
 ])
@@ -142,4 +143,5 @@ def test_null_handles_are_rejected(bfs):
     assert lib.bfsearch_plan_get_info(None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_plan_kernel_info(None, 0, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_job_poll(None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_fetch_projection(None, None, 0, ctypes.byref(nw), ctypes.byref(nt)) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_plan_job_bytes(None, None, 1, None) == bfs.BFS_ERR_INVALID_ARG
