@@ -66,18 +66,23 @@ def hann(length: int) -> np.ndarray:
 
 
 def chirp_template(f0: float, fdot: float, length: int, fs: float,
-                   taper: bool = True, normalize: bool = True) -> np.ndarray:
+                   taper: bool = True, normalize: bool = True, symmetric: bool = False) -> np.ndarray:
     """Linear chirp template, FP64: h[m] cos(2 pi frac(f0 t + fdot t^2 / 2)), t = m/fs.
 
     Stand-in for the time-sliced spin-down chirps of Sec. 2; f0 is the
     initial frequency (the quantity Table 3 lists per hit).  Sampled as
     written, aliasing included; unit energy when normalize is set.
+    symmetric: the time-symmetric template of the paper's banks (Fig. 1
+    caption), the chirp plus its own time reversal, x[m] + x[L-1-m], which
+    matches ascending and descending chirps alike; normalised after the sum.
     """
     t = np.arange(length, dtype=np.float64) / fs
     cycles = f0 * t + 0.5 * fdot * t * t
     w = np.cos(2.0 * np.pi * (cycles - np.floor(cycles)))
     if taper:
         w = w * hann(length)
+    if symmetric:
+        w = w + w[::-1]
     if normalize:
         e = np.dot(w, w)
         if e > 0:
@@ -95,10 +100,11 @@ def grid_params(n_f0: int, n_fdot: int, f0_range, fdot_range, taus) -> tuple[np.
 
 
 def template_bank(f0: np.ndarray, fdot: np.ndarray, tau: np.ndarray, fs: float,
-                  taper: bool = True, ids=None) -> list[np.ndarray]:
+                  taper: bool = True, ids=None, symmetric: bool = False) -> list[np.ndarray]:
     """Unit-energy chirps for the selected template ids (all when ids is None)."""
     ids = range(len(f0)) if ids is None else ids
-    return [chirp_template(f0[j], fdot[j], int(round(tau[j] * fs)), fs, taper=taper) for j in ids]
+    return [chirp_template(f0[j], fdot[j], int(round(tau[j] * fs)), fs, taper=taper, symmetric=symmetric)
+            for j in ids]
 
 
 # -------------------------------------------------------------- correlation --
@@ -159,14 +165,20 @@ def sigma_eq7(c_half: np.ndarray, n: int) -> np.ndarray:
 
 # --------------------------------------------------------------------- tails --
 
-def threshold_tails(rho: np.ndarray, sigma: float, kappa: float) -> np.ndarray:
-    """Lags n with |rho_n| > kappa * sigma (Eq. (9) on the absolute value), ascending."""
+def threshold_tails(rho: np.ndarray, sigma: float, kappa: float, kappa_hi: float = 0.0) -> np.ndarray:
+    """Lags n with |rho_n| > kappa * sigma (Eq. (9) on the absolute value), ascending.
+
+    kappa_hi > 0 keeps a finite band instead, kappa sigma < |rho_n| < kappa_hi sigma: the
+    generalisation the paper proposes for deep searches (Sec. 4, last paragraphs)."""
     if not sigma > 0:
         return np.zeros(0, dtype=np.int64)
-    return np.nonzero(np.abs(rho) > kappa * sigma)[0]
+    keep = np.abs(rho) > kappa * sigma
+    if kappa_hi > 0:
+        keep &= np.abs(rho) < kappa_hi * sigma
+    return np.nonzero(keep)[0]
 
 
-def search(segments, templates, kappa: float, keep_rho: bool = False, chunk: int = 128):
+def search(segments, templates, kappa: float, keep_rho: bool = False, chunk: int = 128, kappa_hi: float = 0.0):
     """Full oracle: every segment against every template.
 
     segments: list of 1-D arrays (FP32 inputs are upcast exactly to FP64).
@@ -200,7 +212,7 @@ def search(segments, templates, kappa: float, keep_rho: bool = False, chunk: int
             sig[s, js] = sg
             sig_f[s, js] = sigma_parseval(c, n)
             for r, j in enumerate(js):
-                lags = threshold_tails(rho[r], sg[r], kappa)
+                lags = threshold_tails(rho[r], sg[r], kappa, kappa_hi)
                 if lags.size:
                     t = np.zeros(lags.size, dtype=TAIL_DTYPE)
                     t["segment"] = s

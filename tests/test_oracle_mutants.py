@@ -24,7 +24,7 @@ MUTANTS = {
     "parseval_no_factor2": ("+ 2.0 * np.sum(p[..., 1:n // 2], axis=-1)", "+ np.sum(p[..., 1:n // 2], axis=-1)"),
     "parseval_drops_dc": ("s = p[..., 0] + p[..., n // 2] +", "s = p[..., n // 2] +"),
     "threshold_ge": ("np.abs(rho) > kappa * sigma", "np.abs(rho) >= kappa * sigma"),
-    "threshold_no_abs": ("np.nonzero(np.abs(rho) > kappa * sigma)", "np.nonzero(rho > kappa * sigma)"),
+    "threshold_no_abs": ("keep = np.abs(rho) > kappa * sigma", "keep = rho > kappa * sigma"),
     "chirp_no_half": ("cycles = f0 * t + 0.5 * fdot * t * t", "cycles = f0 * t + fdot * t * t"),
     "chirp_fdot_sign": ("cycles = f0 * t + 0.5 * fdot * t * t", "cycles = f0 * t - 0.5 * fdot * t * t"),
     "hann_periodic": ("np.cos(2.0 * np.pi * m / (length - 1))", "np.cos(2.0 * np.pi * m / length)"),
@@ -32,6 +32,8 @@ MUTANTS = {
                         "return f0s[j % int(n_f0)], fds[j // int(n_f0)]"),
     "no_normalisation": ("w = w / np.sqrt(e)", "w = w / e"),
     "direct_lag_reversed": ("rho += w[m] * np.roll(y, -m)", "rho += w[m] * np.roll(y, m)"),
+    "symmetric_not_added": ("w = w + w[::-1]", "w = w[::-1]"),
+    "band_inclusive": ("keep &= np.abs(rho) < kappa_hi * sigma", "keep &= np.abs(rho) <= kappa_hi * sigma"),
     "projection_raw_rho": ("v = abs(r) / float(sigma[s, j])", "v = abs(r)"),
     "projection_signed": ("v = abs(r) / float(sigma[s, j])", "v = r / float(sigma[s, j])"),
     "projection_highest_id": ("if v > bv or (v == bv and j < bj):", "if v > bv or (v == bv and j > bj):"),
@@ -53,6 +55,8 @@ PIN_TESTS = [
     (pins.test_sigma_expectation_equals_inband_template_energy, [()]),
     (pins.test_max_projection_equals_brute_force_argmax, [()]),
     (pins.test_max_projection_ties_scale_and_sign, [()]),
+    (pins.test_time_symmetric_template_mirrors_correlation_of_reversed_data, [()]),
+    (pins.test_band_threshold_keeps_only_the_band, [()]),
 ]
 
 

@@ -300,3 +300,39 @@ def test_max_projection_ties_scale_and_sign():
     assert np.array_equal(p1["lag"], one["tails"]["lag"]) and np.all(p1["template"] == 0)
     np.testing.assert_allclose(p1["snr"], one["tails"]["rho"] / one["sigma"][0, 0], rtol=1e-14)
     assert np.any(p1["snr"] < 0) and np.any(p1["snr"] > 0)
+
+
+def test_time_symmetric_template_mirrors_correlation_of_reversed_data():
+    # a time-symmetric template (w[m] = w[L-1-m]) correlated with time-reversed data gives the
+    # mirrored correlation: rho_rev[n] = rho[(-n - L) mod N]; a one-way chirp does not
+    n, fs = 256, 4096.0
+    ws = oracle.chirp_template(600.0, 900.0, 64, fs, symmetric=True)
+    wf = oracle.chirp_template(600.0, 900.0, 64, fs)
+    assert np.array_equal(ws, ws[::-1]) and abs(np.dot(ws, ws) - 1.0) < 1e-12
+    y = _rng(23).standard_normal(n)
+    yr = y[::-1].copy()
+    mirror = (-np.arange(n) - len(ws)) % n
+    np.testing.assert_allclose(oracle.correlate_fft(yr, ws), oracle.correlate_fft(y, ws)[mirror], atol=1e-12)
+    assert not np.allclose(oracle.correlate_fft(yr, wf), oracle.correlate_fft(y, wf)[mirror], atol=1e-6)
+    # it responds to the chirp and to its time reversal alike (ascending and descending searches)
+    up = oracle.correlate_fft(np.pad(wf, (0, n - 64)), ws)[0]
+    down = oracle.correlate_fft(np.pad(wf[::-1], (0, n - 64)), ws)[0]
+    assert abs(up - down) < 1e-12 and up > 0.6
+
+
+def test_band_threshold_keeps_only_the_band():
+    r = _rng(24)
+    rho = r.standard_normal(4000)
+    sig = 1.0
+    band = oracle.threshold_tails(rho, sig, 2.0, 2.5)
+    expect = [i for i, v in enumerate(rho) if 2.0 < abs(v) < 2.5]
+    assert band.tolist() == expect and len(expect) > 20
+    # the open band equals the one-sided threshold minus the upper tail
+    hi = oracle.threshold_tails(rho, sig, 2.5 - 1e-15)
+    lo = oracle.threshold_tails(rho, sig, 2.0)
+    assert sorted(set(lo.tolist()) - set(hi.tolist())) == expect
+    # both edges strict: values exactly at kappa sigma or kappa_hi sigma are outside
+    edges = np.array([2.5, -2.5, 2.0, 2.2, -2.3, -2.0])
+    assert oracle.threshold_tails(edges, 1.0, 2.0, 2.5).tolist() == [3, 4]
+    out = oracle.search([rho[:512]], [np.ones(1)], 1.5, kappa_hi=2.0)
+    assert all(1.5 < abs(v) / out["sigma"][0, 0] < 2.0 for v in out["tails"]["rho"])
