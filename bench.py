@@ -96,7 +96,8 @@ def parse():
     return p.parse_args()
 
 
-def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=False):
+def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=False, symmetric=False, kappa=None,
+             kappa_hi=0.0):
     """Plan the workload, then time `steps` steps.  A step is one filter call (segment FFT +
     fused kernel over every template) and the fetch of its sorted tails; up to `depth` steps are
     queued on the stream, so the next step's kernels run while the host fetches and sorts the
@@ -104,10 +105,10 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=Fa
     CUs).  Every timed step completes inside the timed region."""
     from collections import deque
 
-    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
+    grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus, symmetric=symmetric)
     t0 = time.perf_counter()
-    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=precision, tail_capacity=1 << 22,
-                    autotune=True, project=project)
+    plan = bfs.Plan(w.n, w.fs, kappa=w.kappa if kappa is None else kappa, grid=grid, precision=precision,
+                    tail_capacity=1 << 22, autotune=True, project=project, kappa_hi=kappa_hi)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     kernel = plan.kernel_info()
@@ -358,6 +359,15 @@ def main():
                                                  args.depth, project=True)
         line["max_projection"] = {"value": args.steps * k / wallp, "kernel_rate": k / (np.mean(corrp) * 1e-3),
                                   "ms_per_step": wallp / args.steps * 1e3, "lags_per_step": n_peaks}
+        # time-symmetric bank (chirp plus its reversal) and a finite tail band 3 sigma < |rho| < 3.5 sigma
+        walls, builds, corrs, _, n_sym, _ = run_plan(bfs, torch, w, y_dev, args.precision, args.steps, args.warmup,
+                                                    args.depth, symmetric=True)
+        line["symmetric_bank"] = {"value": args.steps * k / walls, "kernel_rate": k / (np.mean(corrs) * 1e-3),
+                                  "bank_build_and_tune_s": builds, "tails_per_step": n_sym}
+        wallb, _, corrb, _, n_band, _ = run_plan(bfs, torch, w, y_dev, args.precision, args.steps, args.warmup,
+                                                args.depth, kappa=3.0, kappa_hi=3.5)
+        line["band_threshold"] = {"kappa": 3.0, "kappa_hi": 3.5, "value": args.steps * k / wallb,
+                                  "kernel_rate": k / (np.mean(corrb) * 1e-3), "tails_per_step": n_band}
     if not args.no_dense_bank and args.workload == "C2":
         line["dense_bank_fp16"] = run_dense_bank(bfs, torch, 3, 1)
     if not args.no_batched and args.workload == "C2":

@@ -70,6 +70,11 @@ typedef enum {
 #define BFS_PLAN_PROJECT 4u  /* per-lag max projection (Sec. 3.3, Eqs. 13-17)
                                 instead of the tail list: see
                                 bfsearch_fetch_projection */
+#define BFS_PLAN_SYMMETRIC 8u /* grid templates symmetric in time: the chirp
+                                 plus its time reversal, x[m] + x[L-1-m],
+                                 normalised after the sum (the paper's bank
+                                 shape, Fig. 1 caption), for ascending and
+                                 descending chirps alike */
 
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
@@ -131,6 +136,10 @@ typedef struct {
                                    that has that many (manual tuning, tests) */
   uint32_t tile;                /* 0: the default (or autotuned) segment tile;
                                    t > 0: t segments per tile at every length */
+  double kappa_hi;              /* 0: tails are |rho| > kappa sigma; > kappa: a
+                                   finite band kappa sigma < |rho| < kappa_hi sigma
+                                   (the deep-search generalisation of Eq. 9 the
+                                   paper proposes in Sec. 4) */
 } bfs_plan_desc;
 
 /* Read-only facts about a plan. */

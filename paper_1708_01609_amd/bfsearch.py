@@ -27,6 +27,7 @@ FP64, FP32, FP32_W16F, FP32_W16B = 0, 1, 2, 3
 PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 PLAN_PROJECT = 4
+PLAN_SYMMETRIC = 8
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
 TAIL_DTYPE = np.dtype(
@@ -60,6 +61,7 @@ class PlanDesc(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("candidate", ctypes.c_uint32),
         ("tile", ctypes.c_uint32),
+        ("kappa_hi", ctypes.c_double),
     ]
 
 
@@ -156,6 +158,7 @@ class Grid:
     fdot_range: tuple[float, float]
     taus: tuple[float, ...]
     taper: bool = True
+    symmetric: bool = False   # chirp plus its time reversal
 
 
 class Plan:
@@ -165,7 +168,7 @@ class Plan:
                  templates: np.ndarray | None = None, precision: str = "f32",
                  tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
                  n_min: int | None = None, graph: bool = False, autotune: bool = False,
-                 candidate: int = 0, tile: int = 0, project: bool = False):
+                 candidate: int = 0, tile: int = 0, project: bool = False, kappa_hi: float = 0.0):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
         d.n_min = int(n_min) if n_min else 0
@@ -174,6 +177,7 @@ class Plan:
         d.flags = (PLAN_GRAPH if graph else 0) | (PLAN_AUTOTUNE if autotune else 0) | (PLAN_PROJECT if project else 0)
         d.candidate = int(candidate)
         d.tile = int(tile)
+        d.kappa_hi = float(kappa_hi)
         keep = []
         if templates is not None:
             t = np.ascontiguousarray(np.atleast_2d(np.asarray(templates, dtype=np.float64)))
@@ -191,6 +195,8 @@ class Plan:
             d.n_tau = len(taus)
             d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
             d.taper = 1 if grid.taper else 0
+            if grid.symmetric:
+                d.flags |= PLAN_SYMMETRIC
         self.precision = precision
         self.sample_dtype = "float64" if precision == "f64" else "float32"
         self.tail_capacity = int(tail_capacity)

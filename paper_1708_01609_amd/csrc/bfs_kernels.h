@@ -49,14 +49,15 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
 // src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
 // samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
 // The chirp source writes the FP64 sum of x^2 over the samples it made to
-// energy[b] (the unpack turns it into the unit-norm scale).
+// energy[b] (the unpack turns it into the unit-norm scale); with symmetric
+// set it synthesises the chirp plus its time reversal, x[m] + x[L-1-m].
 template <typename T, class F, int SRC>
 __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     const void* __restrict__ src, uint64_t src_stride, uint32_t src_len, const uint64_t* __restrict__ seg_ptr,
     const double* __restrict__ f0, const double* __restrict__ fdot, const uint32_t* __restrict__ len,
     double fs, int taper, uint32_t first,
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    cx<T>* __restrict__ out, double* __restrict__ energy, int split) {
+    cx<T>* __restrict__ out, double* __restrict__ energy, int split, int symmetric) {
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
@@ -84,6 +85,10 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
         if (2 * kk < L) {
           a = chirp_sample(2 * kk, L, pf0, pfd, fs, taper);
           bb = chirp_sample(2 * kk + 1, L, pf0, pfd, fs, taper);
+          if (symmetric) {  // plus the time reversal: x[m] + x[L-1-m]
+            a += chirp_sample(L - 1 - 2 * kk, L, pf0, pfd, fs, taper);
+            if (2 * kk + 1 < L) bb += chirp_sample(L - 2 - 2 * kk, L, pf0, pfd, fs, taper);
+          }
         }
         acc += a * a + bb * bb;
         v[c * F::R1 + k2] = {T(a), T(bb)};
@@ -393,7 +398,8 @@ __device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, cons
   }
 }
 
-// Stage 3, threshold: keep |z| > thr (thr = kappa sqrt(S) in z units) with
+// Stage 3, threshold: keep thr < |z| < thr_hi (thr = kappa sqrt(S) in z units;
+// thr_hi = kappa_hi sqrt(S) for a finite band, else +inf) with
 // one ballot per value and one atomicAdd per wave and value; records past
 // cap are counted but not written.  any: this thread may hold a tail.
 // With prow set (per-lag max projection) a tail is not written to the list:
@@ -403,7 +409,7 @@ __device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, cons
 // template id, and the result does not depend on the order of the updates.
 // rootS = sqrt(S) = N sigma, so |rho| / sigma = |z| / rootS.
 template <class F, typename T, class Z>
-__device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool any, uint32_t s, uint32_t j,
+__device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_hi, bool any, uint32_t s, uint32_t j,
                                            double N, tail_rec* __restrict__ tails,
                                            unsigned long long* __restrict__ counter, uint64_t cap,
                                            unsigned long long* __restrict__ prow, double rootS, int t) {
@@ -418,7 +424,7 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, bool an
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const T val = h ? a.y : a.x;
-        const bool pred = any && (fabs(val) > thr);
+        const bool pred = any && (fabs(val) > thr) && (fabs(val) < thr_hi);
         const uint64_t mask = __ballot(pred);
         if (mask) {
           const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -527,7 +533,8 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
-    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, T* __restrict__ rho_dense) {
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
+    T* __restrict__ rho_dense) {
   constexpr int M = F::M;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -553,13 +560,14 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     emit_dense<F, T>(z, 0u, N, rr, t);
   } else {
     const T thr = T(kappa * rootS);
+    const T thr_hi = kappa_hi > 0.0 ? T(kappa_hi * rootS) : T(INFINITY);
     T mx = T(0);
 #pragma unroll
     for (int i = 0; i < F::P; ++i) mx = fmax(mx, fmax(fabs(v[i].x), fabs(v[i].y)));
     const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
       unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
-      emit_tails<F, T>(z, 0u, thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z, 0u, thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
     }
   }
 }
@@ -577,7 +585,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
-    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, T* __restrict__ rho_dense) {
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
+    T* __restrict__ rho_dense) {
   constexpr int H = F::M, M = 2 * H;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -631,6 +640,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     emit_dense<F, T>(z_hi, uint32_t(H), N, rr, t);
   } else {
     const T thr = T(kappa * rootS);
+    const T thr_hi = kappa_hi > 0.0 ? T(kappa_hi * rootS) : T(INFINITY);
     T mx = T(0);
 #pragma unroll
     for (int i = 0; i < F::P; ++i) {
@@ -640,8 +650,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
       unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
-      emit_tails<F, T>(z_lo, 0u, thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
-      emit_tails<F, T>(z_hi, uint32_t(H), thr, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z_lo, 0u, thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z_hi, uint32_t(H), thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
     }
   }
 }

@@ -45,6 +45,7 @@ struct FwdArgs {
   const void* tw2;
   void* out;
   double* energy;
+  int symmetric;            // chirp source: add the time reversal
 };
 
 struct CorrArgs {
@@ -63,6 +64,7 @@ struct CorrArgs {
   uint64_t cap;
   unsigned long long* proj;  // projection keys (null: tail list)
   const uint64_t* proj_off;  // per grid row: offset of its lags in proj
+  double kappa_hi;           // > 0: upper edge of a finite tail band
   void* rho;
 };
 
@@ -93,13 +95,13 @@ struct Impl {
     auto* out = static_cast<cx<T>*>(a.out);
     if (src == SRC_SAMPLES)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
     else if (src == SRC_CHIRP)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
     else
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
     return hipGetLastError();
   }
   static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
@@ -126,10 +128,10 @@ struct Impl {
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
     if constexpr (SPLIT)
       hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, a.kappa_hi, rho);
     else
       hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, rho);
+                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, a.kappa_hi, rho);
   }
   // 1-D grid in the XCD-aware order of tile_map: 8 ceil(K/8) S workgroups
   static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
@@ -366,7 +368,7 @@ struct bfs_plan {
   int device = 0;
   uint32_t n_max = 0, n_min = 0, K = 0;
   bfs_precision prec = BFS_FP32;
-  double kappa = 0.0;
+  double kappa = 0.0, kappa_hi = 0.0;
   uint64_t cap = 0;
   std::vector<SizePlan> sizes;  // ascending N: sizes[i].N = n_min << i
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
@@ -458,7 +460,9 @@ bfs_status validate(const bfs_plan_desc* d) {
   if (d->tail_capacity < 1) return BFS_ERR_INVALID_ARG;
   if (d->precision < BFS_FP64 || d->precision > BFS_FP32_W16B) return BFS_ERR_INVALID_ARG;
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
-  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT)) return BFS_ERR_INVALID_ARG;
+  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT | BFS_PLAN_SYMMETRIC))
+    return BFS_ERR_INVALID_ARG;
+  if (!std::isfinite(d->kappa_hi) || (d->kappa_hi != 0.0 && !(d->kappa_hi > d->kappa))) return BFS_ERR_INVALID_ARG;
   if (d->candidate > uint32_t(MAX_CANDIDATES)) return BFS_ERR_INVALID_ARG;
   if (d->tile > 65535) return BFS_ERR_INVALID_ARG;
   if (d->explicit_templates) {
@@ -673,6 +677,7 @@ bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
           a.len = dlen;
           a.fs = d->fs;
           a.taper = int(d->taper);
+          a.symmetric = (d->flags & BFS_PLAN_SYMMETRIC) ? 1 : 0;
           a.first = uint32_t(j0);
           a.tw1 = sp.tw1;
           a.tw2 = sp.tw2;
@@ -882,6 +887,7 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.K = p->K;
     c.tile = g.sp->tile;
     c.kappa = p->kappa;
+    c.kappa_hi = p->kappa_hi;
     c.sigma = dense ? sigma : b->sigma;
     c.tails = b->tails;
     c.counter = b->counter;
@@ -990,6 +996,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   p->K = d->explicit_templates ? d->n_explicit : d->n_f0 * d->n_fdot;
   p->prec = d->precision;
   p->kappa = d->kappa;
+  p->kappa_hi = d->kappa_hi;
   p->cap = d->tail_capacity;
   for (uint32_t n = p->n_min; n <= p->n_max; n <<= 1) {
     SizePlan sp;

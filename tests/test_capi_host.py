@@ -87,7 +87,9 @@ def _desc(bfs, **kw):
     ("n_min", 3000),        # not a power of two
     ("n_min", 1 << 17),     # above n
     ("n_min", 2048),        # shorter than the 4096-sample templates
-    ("flags", 8),           # unknown flag
+    ("flags", 16),          # unknown flag
+    ("kappa_hi", 4.0),      # band edge below kappa
+    ("kappa_hi", float("inf")),
     ("candidate", 99),      # no such kernel candidate
     ("tile", 1 << 20),      # tile beyond the segment limit
 ])
@@ -104,7 +106,7 @@ def test_plan_desc_layout_matches_header(bfs):
     off = {f: getattr(bfs.PlanDesc, f).offset for f, _ in bfs.PlanDesc._fields_}
     assert off["n"] == 0 and off["n_min"] == 4 and off["fs"] == 8
     assert off["flags"] == off["device"] + 4 and off["candidate"] == off["flags"] + 4
-    assert off["tile"] == off["candidate"] + 4
+    assert off["tile"] == off["candidate"] + 4 and off["kappa_hi"] % 8 == 0 and off["kappa_hi"] > off["tile"]
     assert ctypes.sizeof(bfs.PlanDesc) % 8 == 0
     assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4
 

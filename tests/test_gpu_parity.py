@@ -476,3 +476,68 @@ def test_workgroup_order_tiles_cover_every_correlation_once(bfs):
     assert np.all(res[1][1] > 0) and np.max(np.abs(res[1][1] - out["sigma"]) / out["sigma"]) <= TOL["f32"]
     compare_tails(res[1][0], out["tails"], out["sigma"], kappa, TOL["f32"],
                   lambda s, j: oracle.correlate_fft(ys[s].astype(np.float64), tw[j]))
+
+
+def test_time_symmetric_bank_spectra_and_c1_search(bfs):
+    # time-symmetric templates (chirp plus its reversal) synthesised on the device: spectra at
+    # every plan length against the oracle, and the C1 search in FP64 against the oracle
+    w = get_workload("C4")
+    grid = bfs.Grid(4, 4, w.f0_range, w.fdot_range, w.taus, symmetric=True)
+    f0 = np.repeat(np.linspace(*w.f0_range, 4), 4)
+    fd = np.tile(np.linspace(*w.fdot_range, 4), 4)
+    tau = np.array([w.taus[j % len(w.taus)] for j in range(16)])
+    temps = oracle.template_bank(f0, fd, tau, w.fs, symmetric=True)
+    with bfs.Plan(1 << 17, w.fs, kappa=5.0, grid=grid, precision="f32", n_min=1 << 14) as plan:
+        for n in (1 << 14, 1 << 17):
+            spec = plan.spectra(n=n).cpu().numpy()
+            ref = np.fft.rfft(np.array([np.pad(t, (0, n - len(t))) for t in temps]), axis=-1)
+            assert max_rel_err(spec, ref, np.max(np.abs(ref), axis=-1)) <= 2e-6, n
+    c1 = get_workload("C1")
+    y, _ = make_segment(c1, 0)
+    g1 = bfs.Grid(c1.n_f0, c1.n_fdot, c1.f0_range, c1.fdot_range, c1.taus, symmetric=True)
+    with bfs.Plan(c1.n, c1.fs, kappa=c1.kappa, grid=g1, precision="f64") as plan:
+        with plan.filter(_dev(y, np.float64)) as job:
+            tails, _ = job.fetch_tails()
+            sig = job.fetch_sigma()
+    f0, fd, tau = c1.template_params()
+    bank = oracle.template_bank(f0, fd, tau, c1.fs, symmetric=True)
+    out = oracle.search([y], bank, c1.kappa, keep_rho=True)
+    assert np.max(np.abs(sig - out["sigma"]) / out["sigma"]) <= TOL["f64"]
+    common, band = compare_tails(tails, out["tails"], out["sigma"], c1.kappa, TOL["f64"],
+                                 lambda s, j: out["rho"][s][j])
+    assert common > 50 and band <= 2
+
+
+def test_band_threshold_matches_oracle(bfs):
+    # finite band kappa sigma < |rho| < kappa_hi sigma (deep-search form) on the C2 segment
+    w = get_workload("C2")
+    y, _ = make_segment(w, 0)
+    kappa, kappa_hi = 3.0, 3.5
+    grid = bfs.Grid(16, 16, w.f0_range, w.fdot_range, w.taus)
+    f0 = np.repeat(np.linspace(*w.f0_range, 16), 16)
+    fd = np.tile(np.linspace(*w.fdot_range, 16), 16)
+    temps = oracle.template_bank(f0, fd, np.full(256, 1.0), w.fs)
+    with bfs.Plan(w.n, w.fs, kappa=kappa, kappa_hi=kappa_hi, grid=grid, precision="f32",
+                  tail_capacity=1 << 22) as plan:
+        with plan.filter(_dev(y, np.float32)) as job:
+            tails, total = job.fetch_tails()
+    out = oracle.search([y.astype(np.float64)], temps, kappa, kappa_hi=kappa_hi)
+    sig = out["sigma"][0]
+    floor = np.array([sigma_floor(t, y) for t in temps])
+    tol = TOL["f32"] * np.maximum(sig, floor) / sig  # in units of sigma
+    g = {(int(j), int(n)): float(r) for j, n, r in zip(tails["template"], tails["lag"], tails["rho"])}
+    o = {(int(j), int(n)): float(r) for j, n, r in zip(out["tails"]["template"], out["tails"]["lag"], out["tails"]["rho"])}
+    rows = {}
+
+    def near_edge(j, n):
+        if j not in rows:
+            rows[j] = oracle.correlate_fft(y.astype(np.float64), temps[j]) / sig[j]
+        a = abs(rows[j][n])
+        return min(abs(a - kappa), abs(a - kappa_hi)) <= tol[j]
+
+    only = (g.keys() - o.keys()) | (o.keys() - g.keys())
+    assert all(near_edge(j, n) for j, n in only)
+    assert all(abs(g[k] - o[k]) <= TOL["f32"] * max(sig[k[0]], floor[k[0]]) for k in g.keys() & o.keys())
+    assert all(kappa < abs(r) / sig[j] < kappa_hi + tol[j] for (j, n), r in g.items())
+    print(f"band: {total} GPU tails, {len(o)} oracle, {len(only)} differ within the band edges")
+    assert len(g.keys() & o.keys()) > 1000 and len(only) <= len(o) // 100
