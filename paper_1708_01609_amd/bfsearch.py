@@ -338,7 +338,7 @@ class Job:
     def fetch_tails(self, capacity: int | None = None, allow_overflow: bool = False):
         """Tails sorted by (segment, template, lag) as a TAIL_DTYPE array, and the exact total."""
         cap = self.plan.tail_capacity if capacity is None else int(capacity)
-        out = np.zeros(cap, dtype=TAIL_DTYPE)
+        out = np.empty(cap, dtype=TAIL_DTYPE)  # only the first n_written records are filled
         nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
         st = _lib.bfsearch_fetch_tails(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw),
                                        ctypes.byref(nt))
@@ -351,7 +351,7 @@ class Job:
         """Per-lag max projection (projection plans): PEAK_DTYPE records sorted by (segment, lag), one
         per lag carrying a tail, and the exact number of such lags."""
         cap = sum(self.lengths) if capacity is None else int(capacity)
-        out = np.zeros(cap, dtype=PEAK_DTYPE)
+        out = np.empty(cap, dtype=PEAK_DTYPE)  # only the first n_written records are filled
         nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
         st = _lib.bfsearch_fetch_projection(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw),
                                             ctypes.byref(nt))

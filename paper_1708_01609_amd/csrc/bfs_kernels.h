@@ -399,9 +399,10 @@ __device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, cons
 }
 
 // Stage 3, threshold: keep thr < |z| < thr_hi (thr = kappa sqrt(S) in z units;
-// thr_hi = kappa_hi sqrt(S) for a finite band, else +inf) with
-// one ballot per value and one atomicAdd per wave and value; records past
-// cap are counted but not written.  any: this thread may hold a tail.
+// thr_hi = kappa_hi sqrt(S) for a finite band, else +inf).  Called by the whole
+// wave when some lane may hold a tail (any).  The wave counts its tails first,
+// reserves them with one atomicAdd and a prefix sum of the per-lane counts,
+// then every lane writes its own; records past cap are counted but not written.
 // With prow set (per-lag max projection) a tail is not written to the list:
 // it raises prow[lag] with atomicMax to the key
 //   (float bits of |rho| / sigma) << 32 | (0x7fffffff - j) << 1 | (rho < 0),
@@ -414,7 +415,26 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_h
                                            unsigned long long* __restrict__ counter, uint64_t cap,
                                            unsigned long long* __restrict__ prow, double rootS, int t) {
   const int lane = t & 63;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  auto is_tail = [&](T val) { return any && (fabs(val) > thr) && (fabs(val) < thr_hi); };
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < F::P; ++i) {
+    const cx<T> a = z(i);
+    cnt += uint32_t(is_tail(a.x)) + uint32_t(is_tail(a.y));
+  }
+  uint32_t incl = cnt;  // inclusive prefix sum over the wave's lanes
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  if (total == 0) return;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(counter, (unsigned long long)total);
+  base = __shfl(base, 0, 64);
+  if (cnt == 0) return;
+  uint64_t idx = base + (incl - cnt);
 #pragma unroll
   for (int c = 0; c < F::C2; ++c) {
 #pragma unroll
@@ -424,35 +444,24 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_h
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const T val = h ? a.y : a.x;
-        const bool pred = any && (fabs(val) > thr) && (fabs(val) < thr_hi);
-        const uint64_t mask = __ballot(pred);
-        if (mask) {
-          const int leader = __ffsll((unsigned long long)mask) - 1;
-          unsigned long long base = 0;
-          if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-          base = __shfl(base, leader, 64);
-          if (pred) {
-            const uint32_t lag = 2 * n + uint32_t(h);
-            if (prow) {
-              const float snr = float(fabs(double(val)) / rootS);
-              const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(snr)) << 32) |
-                                             (static_cast<unsigned long long>(0x7fffffffu - j) << 1) |
-                                             (val < T(0) ? 1ull : 0ull);
-              atomicMax(prow + lag, key);
-            } else {
-              const uint64_t idx = base + __popcll(mask & below);
-              if (idx < cap) {
-                tail_rec r;
-                r.segment = s;
-                r.template_id = j;
-                r.lag = lag;
-                r.reserved = 0;
-                r.rho = double(val) / N;
-                tails[idx] = r;
-              }
-            }
-          }
+        if (!is_tail(val)) continue;
+        const uint32_t lag = 2 * n + uint32_t(h);
+        if (prow) {
+          const float snr = float(fabs(double(val)) / rootS);
+          const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(snr)) << 32) |
+                                         (static_cast<unsigned long long>(0x7fffffffu - j) << 1) |
+                                         (val < T(0) ? 1ull : 0ull);
+          atomicMax(prow + lag, key);
+        } else if (idx < cap) {
+          tail_rec r;
+          r.segment = s;
+          r.template_id = j;
+          r.lag = lag;
+          r.reserved = 0;
+          r.rho = double(val) / N;
+          tails[idx] = r;
         }
+        ++idx;
       }
     }
   }

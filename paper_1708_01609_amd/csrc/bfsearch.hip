@@ -967,6 +967,53 @@ bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, vo
   return BFS_OK;
 }
 
+// Tails in (segment, template_id, lag) order.  The device writes them in
+// whatever order the atomics hand out slots; sorting makes the result
+// deterministic.  LSD radix sort (16-bit digits) of the packed key
+// segment << 48 | template_id << 17 | lag when every field fits (segments
+// < 2^16, templates < 2^31, lags < 2^17), else a comparison sort.
+void sort_tails(bfs_tail* t, uint64_t n) {
+  auto less = [](const bfs_tail& a, const bfs_tail& c) {
+    if (a.segment != c.segment) return a.segment < c.segment;
+    if (a.template_id != c.template_id) return a.template_id < c.template_id;
+    return a.lag < c.lag;
+  };
+  bool fits = n < (1ull << 32);
+  for (uint64_t i = 0; i < n && fits; ++i)
+    fits = t[i].segment < (1u << 16) && t[i].template_id < (1u << 31) && t[i].lag < (1u << 17);
+  if (!fits || n < 4096) {
+    std::sort(t, t + n, less);
+    return;
+  }
+  std::vector<uint64_t> key(n), key2(n);
+  std::vector<uint32_t> idx(n), idx2(n);
+  for (uint64_t i = 0; i < n; ++i) {
+    key[i] = (uint64_t(t[i].segment) << 48) | (uint64_t(t[i].template_id) << 17) | t[i].lag;
+    idx[i] = uint32_t(i);
+  }
+  std::vector<uint64_t> count(1u << 16);
+  for (int shift = 0; shift < 64; shift += 16) {
+    std::fill(count.begin(), count.end(), 0);
+    for (uint64_t i = 0; i < n; ++i) ++count[(key[i] >> shift) & 0xffffu];
+    if (*std::max_element(count.begin(), count.end()) == n) continue;  // one digit value: already ordered
+    uint64_t sum = 0;
+    for (auto& c : count) {
+      const uint64_t v = c;
+      c = sum;
+      sum += v;
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+      const uint64_t d = (key[i] >> shift) & 0xffffu;
+      key2[count[d]] = key[i];
+      idx2[count[d]++] = idx[i];
+    }
+    key.swap(key2);
+    idx.swap(idx2);
+  }
+  std::vector<bfs_tail> tmp(t, t + n);
+  for (uint64_t i = 0; i < n; ++i) t[i] = tmp[idx[i]];
+}
+
 }  // namespace
 
 extern "C" {
@@ -1155,11 +1202,7 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
     HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
     HIP_TRY(hipStreamSynchronize(p->copy_stream));
   }
-  std::sort(tmp, tmp + on_dev, [](const bfs_tail& a, const bfs_tail& c) {
-    if (a.segment != c.segment) return a.segment < c.segment;
-    if (a.template_id != c.template_id) return a.template_id < c.template_id;
-    return a.lag < c.lag;
-  });
+  sort_tails(tmp, on_dev);
   const uint64_t nw = std::min<uint64_t>(on_dev, capacity);
   if (nw) std::memcpy(out_host, tmp, nw * sizeof(bfs_tail));
   *n_written = nw;

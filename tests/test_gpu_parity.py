@@ -541,3 +541,22 @@ def test_band_threshold_matches_oracle(bfs):
     assert all(kappa < abs(r) / sig[j] < kappa_hi + tol[j] for (j, n), r in g.items())
     print(f"band: {total} GPU tails, {len(o)} oracle, {len(only)} differ within the band edges")
     assert len(g.keys() & o.keys()) > 1000 and len(only) <= len(o) // 100
+
+
+def test_many_tails_come_back_complete_and_sorted(bfs):
+    # kappa = 0 on 3 segments x 5 templates x 4096 lags: 61,440 tails, all written by the
+    # wave-aggregated compaction and returned in (segment, template, lag) order
+    n, S, K = 4096, 3, 5
+    rng = np.random.default_rng(15)
+    ys = rng.standard_normal((S, n)).astype(np.float32)
+    temps = rng.standard_normal((K, 300))
+    with bfs.Plan(n, 4096.0, kappa=0.0, templates=temps, precision="f32", tail_capacity=S * K * n) as plan:
+        with plan.filter(_dev(ys, np.float32)) as job:
+            tails, total = job.fetch_tails()
+        rho, _ = plan.correlate_dense(_dev(ys, np.float32))
+        rho = rho.cpu().numpy()
+    assert total == S * K * n == len(tails)
+    assert np.array_equal(tails["segment"], np.repeat(np.arange(S), K * n))
+    assert np.array_equal(tails["template"], np.tile(np.repeat(np.arange(K), n), S))
+    assert np.array_equal(tails["lag"], np.tile(np.arange(n), S * K))
+    assert np.array_equal(tails["rho"].astype(np.float32), rho.reshape(-1))
