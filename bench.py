@@ -230,10 +230,13 @@ def run_serving(bfs, torch, args):
     # warm the executor's streams and the job-buffer pool
     serve(ex, reqs[: 2 * args.max_batch], slots=args.slots, max_batch=args.max_batch, budget_bytes=budget,
           speed=1e6)
+    def report(done, total, wall):
+        print(f"serving: {done}/{total} requests after {wall:.0f} s", file=sys.stderr, flush=True)
+
     rt = serve(ex, [r for r in reqs if r.arrival < args.serve_seconds], slots=args.slots,
-               max_batch=args.max_batch, budget_bytes=budget, speed=1.0)
+               max_batch=args.max_batch, budget_bytes=budget, speed=1.0, progress=report)
     sat = serve(ex, [r for r in reqs if r.arrival < args.serve_compressed_seconds], slots=args.slots,
-                max_batch=args.max_batch, budget_bytes=budget, speed=args.serve_speed)
+                max_batch=args.max_batch, budget_bytes=budget, speed=args.serve_speed, progress=report)
     k = w.n_templates
     out = {"workload": f"C5: {w.description}", "bank_bytes": plan.bank_bytes, "bank_build_and_tune_s": build_s,
            "slots": args.slots, "max_batch": args.max_batch, "hbm_budget_bytes_jobs": budget,

@@ -315,7 +315,9 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
   }
 
   const int lane = t & 63;
-  const bool wave0 = t < 64;
+  // wave-uniform (readfirstlane), so the other waves branch around the fixups
+  // instead of issuing them with an empty exec mask
+  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
     const cx<T> bu = tw_u[bu_mul * cols[c] + bu_add];

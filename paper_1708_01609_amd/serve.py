@@ -91,13 +91,15 @@ class ServeStats:
 
 
 def serve(executor, requests, slots: int = 4, max_batch: int = 16, budget_bytes: int = 0,
-          speed: float = 1.0, poll_s: float = 2e-4, clock=time.perf_counter, sleep=time.sleep) -> ServeStats:
+          speed: float = 1.0, poll_s: float = 2e-4, clock=time.perf_counter, sleep=time.sleep,
+          progress=None, progress_every_s: float = 30.0) -> ServeStats:
     """Replay `requests` (arrival times in stream seconds) at `speed` x real time and serve them.
 
     budget_bytes: device bytes the in-flight jobs may hold together (0: no limit beyond the
     executor's own).  A request whose job alone exceeds the budget is rejected.  Returns
     per-request results and totals; latencies are wall-clock seconds from the request's
-    (scaled) arrival to its results on the host."""
+    (scaled) arrival to its results on the host.  progress(done, total, wall_s), if given,
+    is called about every progress_every_s seconds."""
     if slots < 1 or max_batch < 1 or speed <= 0:
         raise ValueError("slots, max_batch and speed must be positive")
     stats = ServeStats()
@@ -107,12 +109,17 @@ def serve(executor, requests, slots: int = 4, max_batch: int = 16, budget_bytes:
     inflight: dict = {}     # slot -> (handle, requests, bytes, admit_wall, job id)
     inflight_bytes = 0
     t0 = clock()
+    next_report = t0 + progress_every_s
+    n_total = len(pending)
 
     def arrival_wall(r):
         return t0 + r.arrival / speed
 
     while pending or waiting or inflight:
         now = clock()
+        if progress is not None and now >= next_report:
+            progress(len(stats.results) + len(stats.rejected), n_total, now - t0)
+            next_report = now + progress_every_s
         while pending and arrival_wall(pending[0]) <= now:
             waiting.append(pending.popleft())
         progressed = False
