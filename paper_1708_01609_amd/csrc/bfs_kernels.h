@@ -29,7 +29,7 @@ struct tail_rec {
   double rho;
 };
 
-enum Source : int { SRC_SAMPLES = 0, SRC_CHIRP = 1, SRC_EXPLICIT = 2 };
+enum Source : int { SRC_SAMPLES = 0, SRC_CHIRP = 1, SRC_EXPLICIT = 2, SRC_CHIRP_SYM = 3 };
 
 // ---------------------------------------------------------------- forward --
 // x[m] for the chirp source: h[m] cos(2 pi frac(f0 t + fdot t^2 / 2)), t = m/fs,
@@ -49,15 +49,15 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
 // src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
 // samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
 // The chirp source writes the FP64 sum of x^2 over the samples it made to
-// energy[b] (the unpack turns it into the unit-norm scale); with symmetric
-// set it synthesises the chirp plus its time reversal, x[m] + x[L-1-m].
+// energy[b] (the unpack turns it into the unit-norm scale); SRC_CHIRP_SYM
+// synthesises the chirp plus its time reversal, x[m] + x[L-1-m].
 template <typename T, class F, int SRC>
 __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     const void* __restrict__ src, uint64_t src_stride, uint32_t src_len, const uint64_t* __restrict__ seg_ptr,
     const double* __restrict__ f0, const double* __restrict__ fdot, const uint32_t* __restrict__ len,
     double fs, int taper, uint32_t first,
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    cx<T>* __restrict__ out, double* __restrict__ energy, int split, int symmetric) {
+    cx<T>* __restrict__ out, double* __restrict__ energy, int split) {
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_PLAIN>(t, c);
 
   // ---- load (source stage): element (col, k2) is z_kk, kk = cs (col + S1 k2) + half
-  if constexpr (SRC == SRC_CHIRP) {
+  if constexpr (SRC == SRC_CHIRP || SRC == SRC_CHIRP_SYM) {
     const uint32_t j = first + item;
     const double pf0 = f0[j], pfd = fdot[j];
     const int L = int(len[j]);
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
         if (2 * kk < L) {
           a = chirp_sample(2 * kk, L, pf0, pfd, fs, taper);
           bb = chirp_sample(2 * kk + 1, L, pf0, pfd, fs, taper);
-          if (symmetric) {  // plus the time reversal: x[m] + x[L-1-m]
+          if constexpr (SRC == SRC_CHIRP_SYM) {  // plus the time reversal: x[m] + x[L-1-m]
             a += chirp_sample(L - 1 - 2 * kk, L, pf0, pfd, fs, taper);
             if (2 * kk + 1 < L) bb += chirp_sample(L - 2 - 2 * kk, L, pf0, pfd, fs, taper);
           }
@@ -124,7 +124,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
   }
 
   fft3_pass1<F, -1>(v, tw1, cols);
-  if constexpr (SRC == SRC_CHIRP) {
+  if constexpr (SRC == SRC_CHIRP || SRC == SRC_CHIRP_SYM) {
     const double s = wave_sum(acc);
     if ((t & 63) == 0) red[t >> 6] = s;
   }
@@ -135,7 +135,7 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
   fft3_ex1_write<F, 1>(v, lds, cols);
   lds_barrier();
   fft3_ex1_read<F, 1>(v, lds, t);
-  if constexpr (SRC == SRC_CHIRP) {
+  if constexpr (SRC == SRC_CHIRP || SRC == SRC_CHIRP_SYM) {
     if (t == 0) {
       double s = 0.0;
       for (int w = 0; w < F::NW; ++w) s += red[w];

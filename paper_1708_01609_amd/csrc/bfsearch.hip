@@ -45,7 +45,6 @@ struct FwdArgs {
   const void* tw2;
   void* out;
   double* energy;
-  int symmetric;            // chirp source: add the time reversal
 };
 
 struct CorrArgs {
@@ -95,13 +94,16 @@ struct Impl {
     auto* out = static_cast<cx<T>*>(a.out);
     if (src == SRC_SAMPLES)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     else if (src == SRC_CHIRP)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+    else if (src == SRC_CHIRP_SYM)
+      hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP_SYM>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     else
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.symmetric);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
     return hipGetLastError();
   }
   static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
@@ -677,13 +679,13 @@ bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
           a.len = dlen;
           a.fs = d->fs;
           a.taper = int(d->taper);
-          a.symmetric = (d->flags & BFS_PLAN_SYMMETRIC) ? 1 : 0;
           a.first = uint32_t(j0);
           a.tw1 = sp.tw1;
           a.tw2 = sp.tw2;
           a.out = scratch;
           a.energy = energy;
-          ok = sp.ks->fwd(expl ? SRC_EXPLICIT : SRC_CHIRP, nb, s, a) == hipSuccess;
+          const int src = expl ? SRC_EXPLICIT : ((d->flags & BFS_PLAN_SYMMETRIC) ? SRC_CHIRP_SYM : SRC_CHIRP);
+          ok = sp.ks->fwd(src, nb, s, a) == hipSuccess;
           ok = ok && sp.ks->unpack_bank(nb, s, scratch, sp.bank, expl ? nullptr : energy, sp.tw_u, j0) == hipSuccess;
         }
       }
