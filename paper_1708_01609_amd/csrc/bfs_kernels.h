@@ -445,7 +445,11 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_h
       const cx<T> a = z(c * F::R3 + mp);
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const T val = h ? a.y : a.x;
+        T val = h ? a.y : a.x;
+        // Opaque to the compiler, so |val| is formed here, one value at a
+        // time, and not hoisted for all 2 P values ahead of the loop (which
+        // doubled the registers the kernel holds).
+        asm volatile("" : "+v"(val));
         if (!is_tail(val)) continue;
         const uint32_t lag = 2 * n + uint32_t(h);
         if (prow) {
