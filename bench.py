@@ -36,7 +36,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
 # for the kernel sources they were taken on (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "e0fcacb034c7d33b": {"f32": 2.2146e9, "f32-w16f": 1.0938e9},
+    "a4c2a4bab30a8f75": {"f32": 2.2012e9, "f32-w16f": 1.0900e9},
 }
 
 
