@@ -193,7 +193,16 @@ bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
  * C = conj(W) Y, sigma by Parseval in FP64 (Eq. 7), the inverse FFT on chip
  * (Eq. 5), the threshold (Eq. 9) and wave-ballot compaction of the tails into
  * the job's device buffer.  Segment ids in tails and sigma are the indices
- * into the caller's arrays.  The segment table is read before return. */
+ * into the caller's arrays.  The segment table is read before return.
+ * Streams: the job starts after the work queued on hip_stream before the
+ * call.  Outside BFS_PLAN_GRAPH plans, the segment transforms run on
+ * hip_stream and the fused kernels on an internal stream of the plan paired
+ * with hip_stream (created on first use, destroyed with the plan), queued
+ * after those transforms; so the next call's transforms overlap this call's
+ * correlations, and work queued later on hip_stream is ordered after the
+ * transforms only.  BFS_PLAN_GRAPH plans replay the whole job on hip_stream.
+ * Wait for the job through the job calls (fetch, poll, timing, release), or a
+ * device-wide synchronisation. */
 bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* seg_offsets,
                            const uint32_t* seg_lengths, uint32_t n_segments, void* hip_stream,
                            bfs_job** out);
@@ -225,7 +234,7 @@ bfs_status bfsearch_fetch_projection(bfs_job* job, bfs_peak* out_host, uint64_t 
 bfs_status bfsearch_fetch_sigma(bfs_job* job, double* out_host);
 
 /* Device time of the job's kernels in milliseconds, measured with HIP events
- * on the job's stream: *corr_ms brackets the fused correlation kernels (the
+ * on the streams the kernels run on: *corr_ms brackets the fused correlation kernels (the
  * whole replayed graph for BFS_PLAN_GRAPH plans), *total_ms the whole job.
  * Waits for the job. */
 bfs_status bfsearch_job_timing(bfs_job* job, float* corr_ms, float* total_ms);

@@ -342,7 +342,9 @@ struct JobBuffers {
   unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
   bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
   uint64_t tails_host_cap = 0;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  // [0] job queued, [1]/[2] around the correlation kernels, [3] job done,
+  // [4] segment transforms done (orders the correlation stream after them)
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   uint64_t bytes = 0;
   hipGraphExec_t gexec = nullptr;  // captured job body (graph plans)
   std::vector<uint64_t> gkey;      // the shape it was captured for
@@ -377,8 +379,13 @@ struct bfs_plan {
   bool graph = false;
   bool project = false;  // per-lag max projection instead of the tail list
   hipStream_t copy_stream = nullptr;
-  hipStream_t capture_stream = nullptr;
+  hipStream_t capture_stream = nullptr;  // graph plans only
   std::mutex capture_mu;  // one capture at a time on capture_stream
+  // Correlation stream paired with each caller stream that queued jobs: a
+  // job's segment transforms run on the caller's stream, its correlation
+  // kernels on the paired stream, so the next job's transforms overlap them.
+  std::mutex stream_mu;
+  std::vector<std::pair<hipStream_t, hipStream_t>> corr_streams;
   std::mutex mu;
   std::vector<JobBuffers*> pool;
   uint64_t live_job_bytes = 0;
@@ -447,6 +454,7 @@ void free_plan(bfs_plan* p) {
   }
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  for (auto& cs : p->corr_streams) (void)hipStreamDestroy(cs.second);
   delete p;
 }
 
@@ -755,6 +763,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   }
   for (int i = 0; i < 4 && st == BFS_OK; ++i)
     if (hipEventCreate(&b->ev[i]) != hipSuccess) st = BFS_ERR_HIP;
+  if (st == BFS_OK && hipEventCreateWithFlags(&b->ev[4], hipEventDisableTiming) != hipSuccess) st = BFS_ERR_HIP;
   if (st != BFS_OK) {
     free_job_buffers(b);
     return st;
@@ -846,11 +855,9 @@ void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, con
   }
 }
 
-// Queue the body of a job on st: counter reset, table upload, then per group
-// the segment transforms and the fused correlation kernel.  ev[1] / ev[2]
-// bracket the correlation kernels when with_events is set.
-bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
-                        hipStream_t st, bool with_events) {
+// Queue the first part of a job on st: counter reset, table upload, the
+// segment transforms of every group.
+bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, hipStream_t st) {
   const uint32_t S = uint32_t(L.seg_len.size());
   const bool project = p->project && !dense;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(2), 0ull);
@@ -863,8 +870,6 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   const uint64_t tbytes = uint64_t(S) * (2 * sizeof(uint64_t) + sizeof(uint32_t));
   HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, tbytes, hipMemcpyHostToDevice, st));
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
-  const auto* dpoff = dptr + S;
-  const auto* dids = reinterpret_cast<const uint32_t*>(dpoff + S);
   char* ybase = static_cast<char*>(b->y);
   for (const Group& g : L.groups) {
     const KernelSet& ks = *g.sp->ks;
@@ -877,7 +882,21 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     HIP_TRY(ks.fwd(SRC_SAMPLES, g.count, st, a));
     HIP_TRY(ks.unpack_y(g.count, st, a.out, yg, g.sp->tw_u));
   }
-  if (with_events) HIP_TRY(hipEventRecord(b->ev[1], st));
+  return BFS_OK;
+}
+
+// Queue the second part on cs: one fused correlation kernel per group, then
+// (projection plans) the compaction of the projection keys.  ev[1] / ev[2]
+// bracket the correlation kernels when with_events is set.
+bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
+                        hipStream_t cs, bool with_events) {
+  const uint32_t S = uint32_t(L.seg_len.size());
+  const bool project = p->project && !dense;
+  const auto* dptr = static_cast<const uint64_t*>(b->meta);
+  const auto* dpoff = dptr + S;
+  const auto* dids = reinterpret_cast<const uint32_t*>(dpoff + S);
+  char* ybase = static_cast<char*>(b->y);
+  if (with_events) HIP_TRY(hipEventRecord(b->ev[1], cs));
   for (const Group& g : L.groups) {
     CorrArgs c{};
     c.bank = g.sp->bank;
@@ -897,18 +916,40 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.proj = project ? b->proj : nullptr;
     c.proj_off = project ? dpoff + g.first : nullptr;
     c.rho = rho;
-    HIP_TRY(g.sp->ks->corr(dense, g.count, st, c));
+    HIP_TRY(g.sp->ks->corr(dense, g.count, cs, c));
   }
-  if (with_events) HIP_TRY(hipEventRecord(b->ev[2], st));
+  if (with_events) HIP_TRY(hipEventRecord(b->ev[2], cs));
   if (project) {
     const uint64_t n = L.need.proj;
     const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(project_compact_kernel, dim3(blocks), dim3(256), 0, st, b->proj, n, b->plist, b->counter + 1,
+    hipLaunchKernelGGL(project_compact_kernel, dim3(blocks), dim3(256), 0, cs, b->proj, n, b->plist, b->counter + 1,
                        n);
     HIP_TRY(hipGetLastError());
   }
-  // the counts travel with the job, so a fetch needs one copy only
-  HIP_TRY(hipMemcpyAsync(b->count_host, b->counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st));
+  return BFS_OK;
+}
+
+// The whole job on one stream (graph capture, dense correlation).
+bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
+                        hipStream_t st, bool with_events) {
+  const bfs_status rs = enqueue_prep(p, b, L, dense, st);
+  if (rs != BFS_OK) return rs;
+  return enqueue_corr(p, b, L, dense, rho, sigma, st, with_events);
+}
+
+// The correlation stream paired with the caller's stream st (created on first
+// use, non-blocking, default priority; destroyed with the plan).
+bfs_status corr_stream(bfs_plan* p, hipStream_t st, hipStream_t* out) {
+  std::lock_guard<std::mutex> lk(p->stream_mu);
+  for (const auto& e : p->corr_streams)
+    if (e.first == st) {
+      *out = e.second;
+      return BFS_OK;
+    }
+  hipStream_t cs = nullptr;
+  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  p->corr_streams.emplace_back(st, cs);
+  *out = cs;
   return BFS_OK;
 }
 
@@ -955,18 +996,45 @@ bfs_status launch_graph(bfs_plan* p, JobBuffers* b, const Layout& L, hipStream_t
   return BFS_OK;
 }
 
+// Queue a job.  Tail and projection jobs outside graph plans split over two
+// streams: the segment transforms on st, the correlation kernels on st's
+// paired stream after them (ev[4]), so st is free for the next job's
+// transforms while this job's correlations run; ev[3] marks the job done.
+// Graph plans and dense correlations keep the whole job on st.  *done_stream
+// is the stream ev[3] was recorded on.
 bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
-                     hipStream_t st) {
+                     hipStream_t st, hipStream_t* done_stream) {
+  *done_stream = st;
   HIP_TRY(hipEventRecord(b->ev[0], st));
   if (p->graph && !dense) {
     const bfs_status rs = launch_graph(p, b, L, st);
     if (rs != BFS_OK) return rs;
-  } else {
+  } else if (dense) {
     const bfs_status rs = enqueue_body(p, b, L, dense, rho, sigma, st, true);
     if (rs != BFS_OK) return rs;
+  } else {
+    hipStream_t cs = nullptr;
+    bfs_status rs = corr_stream(p, st, &cs);
+    if (rs != BFS_OK) return rs;
+    rs = enqueue_prep(p, b, L, false, st);
+    if (rs != BFS_OK) return rs;
+    HIP_TRY(hipEventRecord(b->ev[4], st));
+    HIP_TRY(hipStreamWaitEvent(cs, b->ev[4], 0));
+    *done_stream = cs;
+    rs = enqueue_corr(p, b, L, false, nullptr, nullptr, cs, true);
+    if (rs != BFS_OK) return rs;
   }
-  HIP_TRY(hipEventRecord(b->ev[3], st));
+  HIP_TRY(hipEventRecord(b->ev[3], *done_stream));
   return BFS_OK;
+}
+
+// Copy the job's two counters (tails, projection entries) to the pinned host
+// copy; the job has finished.
+hipError_t read_counters(bfs_plan* p, JobBuffers* b) {
+  hipError_t e = hipMemcpyAsync(b->count_host, b->counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                p->copy_stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->copy_stream);
+  return e;
 }
 
 // Tails in (segment, template_id, lag) order.  The device writes them in
@@ -1081,7 +1149,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   p->graph = (d->flags & BFS_PLAN_GRAPH) != 0;
   p->project = (d->flags & BFS_PLAN_PROJECT) != 0;
   if (hipStreamCreateWithFlags(&p->copy_stream, hipStreamNonBlocking) != hipSuccess ||
-      hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+      (p->graph && hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking) != hipSuccess)) {
     free_plan(p);
     return BFS_ERR_HIP;
   }
@@ -1159,9 +1227,11 @@ bfs_status bfsearch_filter(bfs_plan* p, const void* y_dev, const uint64_t* seg_o
     return rs;
   }
   stage_table(p, y_dev, seg_offsets, L, b->meta_host);
-  rs = queue_job(p, b, L, false, nullptr, nullptr, st);
+  hipStream_t done_st = st;
+  rs = queue_job(p, b, L, false, nullptr, nullptr, st, &done_st);
   if (rs != BFS_OK) {
     (void)hipStreamSynchronize(st);
+    (void)hipStreamSynchronize(done_st);
     put_job_buffers(p, b);
     delete j;
     return rs;
@@ -1184,6 +1254,7 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(hipEventSynchronize(b->ev[3]));
+  HIP_TRY(read_counters(p, b));
   const unsigned long long count = *b->count_host;
   const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
   if (on_dev > b->tails_host_cap) {
@@ -1220,6 +1291,7 @@ bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t ca
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(hipEventSynchronize(b->ev[3]));
+  HIP_TRY(read_counters(p, b));
   const unsigned long long count = b->count_host[1];  // <= the number of lags, the list's size
   std::vector<unsigned long long> list(2 * count);
   if (count) {
@@ -1333,7 +1405,8 @@ bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg
   rs = get_job_buffers(p, L.need, &b);
   if (rs != BFS_OK) return rs;
   stage_table(p, y_dev, nullptr, L, b->meta_host);
-  rs = queue_job(p, b, L, true, rho_dev, sigma_dev, st);
+  hipStream_t done_st = st;
+  rs = queue_job(p, b, L, true, rho_dev, sigma_dev, st, &done_st);
   // the buffers go back to the pool only after the queued kernels finish
   (void)hipStreamSynchronize(st);
   put_job_buffers(p, b);
