@@ -261,17 +261,31 @@ __global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long
 // exp(2 pi i k / N) = tw_u[bu_mul col + bu_add] exp(i pi k2 / R1) (bin
 // k = bu_mul k' + bu_add): one table load per column, a constant rotation per
 // element.
-template <class F, int MAP, int G, typename T, typename TW>
+struct NoHook {
+  __device__ void operator()(int, int) const {}
+};
+
+template <class F, int MAP, int G, typename T, typename TW, bool EARLY_BU = false, class Hook = NoHook>
 __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* cols, const rsrc_t& rW,
                                          const rsrc_t& rY, uint32_t row_off, const cx<T>* __restrict__ tw_u,
-                                         uint32_t bu_mul, uint32_t bu_add, int t) {
+                                         uint32_t bu_mul, uint32_t bu_add, int t, Hook&& before_group = Hook{}) {
   // The loads run one group of G elements ahead of the arithmetic (the
   // autotuner picks G; deeper groups hide more latency, cost registers).
+  // before_group(c, g) runs after group g + 1's loads are issued and before
+  // group g's products overwrite registers c R1 + g G .. + G - 1.  EARLY_BU
+  // requests the repack twiddles before the spectra (for callers that issue
+  // stores in before_group: counters complete in issue order, so the
+  // twiddles' wait then covers none of those stores).
   constexpr int NG = F::R1 / G;
   static_assert(G >= 1 && F::R1 % G == 0 && F::R1 % 2 == 0, "group size");
   constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
   constexpr bool HAS_DC = MAP == MAP_MIRROR;
   T cM = T(0);  // C_M of thread 0 (real)
+  cx<T> bu[F::C1];  // the repack twiddle of each column
+  if constexpr (EARLY_BU) {
+#pragma unroll
+    for (int c = 0; c < F::C1; ++c) bu[c] = tw_u[bu_mul * cols[c] + bu_add];
+  }
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
     const uint32_t col = cols[c];
@@ -290,6 +304,7 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
     static_for<NG>([&](auto gc) {
       constexpr int g = decltype(gc)::value;
       if constexpr (g + 1 < NG) issue(g + 1, (g + 1) & 1);
+      before_group(c, g);
       static_for<G>([&](auto ec) {
         constexpr int e = decltype(ec)::value;
         constexpr int k2 = g * G + e;
@@ -320,7 +335,7 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
   const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
-    const cx<T> bu = tw_u[bu_mul * cols[c] + bu_add];
+    if constexpr (!EARLY_BU) bu[c] = tw_u[bu_mul * cols[c] + bu_add];
     cx<T> carry = {T(0), T(0)};
     static_for<F::R1 / 2>([&](auto kc) {
       constexpr int r1 = decltype(kc)::value;
@@ -345,8 +360,8 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
         const cx<T> u = cmul(tk, bq);
         return cx<T>{a.x - u.y, a.y + u.x};
       };
-      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(bu));
-      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(bu));
+      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(bu[c]));
+      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(bu[c]));
       pin(v[c * F::R1 + r1]);
       pin(v[c * F::R1 + r2]);
       if constexpr (r1 % 4 == 3) sched_fence();
@@ -371,6 +386,9 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
   double S = 0.0;
 #pragma unroll
   for (int w = 0; w < F::NW; ++w) S += red[w];
+  // formed here: otherwise the compiler defers the additions to the sum's
+  // use and keeps the NW partial sums live through the transform
+  asm volatile("" : "+v"(S));
   fft3_ex1_read<F, 0>(v, lds, t);
   lds_barrier();
   fft3_ex1_write<F, 1>(v, lds, cols);
@@ -615,9 +633,13 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   cx<T> v[F::P];
   // E waits in per-thread scratch memory: the array's address escapes into
   // an empty asm statement, so it stays in memory (ordinary cached scratch
-  // accesses) instead of being promoted to registers, and the asm's memory
-  // clobber orders the stores before everything after it.
+  // accesses) instead of being promoted to registers.  The stores go out one
+  // load group at a time inside the odd half's product stage, each after the
+  // next group's loads are issued: vector-memory counters complete in issue
+  // order, so no wait for an odd-half load ever covers an E store issued
+  // after it, and the stores drain under the odd half's arithmetic.
   cx<T> e[F::P];
+  asm volatile("" : : "v"(e) : "memory");
 
   double acc = 0.0;
   uint32_t cols[F::C1];
@@ -625,23 +647,29 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
   corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 2u, 0u, t);
   const double S0 = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
-#pragma unroll
-  for (int i = 0; i < F::P; ++i) e[i] = v[i];
-  asm volatile("" : : "v"(e) : "memory");
-  lds_barrier();  // every wave is done with the even half's LDS before the odd half writes it
 
+  // The odd half derives its lane addresses from an opaque copy of the thread
+  // index, so nothing computed for the even half is kept (spilled) for reuse.
+  int to = t;
+  asm volatile("" : "+v"(to));
   acc = 0.0;
 #pragma unroll
-  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR_ODD>(t, c);
-  corr_pre<F, MAP_MIRROR_ODD, G, T, TW>(v, acc, cols, rW, rY, uint32_t(H), tw_u, 2u, 1u, t);
-  const double S = S0 + corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR_ODD>(to, c);
+  corr_pre<F, MAP_MIRROR_ODD, G, T, TW, true>(v, acc, cols, rW, rY, uint32_t(H), tw_u, 2u, 1u, to, [&](int c, int g) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) e[c * F::R1 + g * G + k] = v[c * F::R1 + g * G + k];
+    asm volatile("" ::: "memory");
+  });
+  asm volatile("" : : "v"(e) : "memory");
+  lds_barrier();  // every wave is done with the even half's LDS before the odd half writes it
+  const double S = S0 + corr_ifft<F>(v, lds, red, cols, tw1, tw2, to, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
 
   // v <- exp(2 pi i n / M) O_n
 #pragma unroll
   for (int c = 0; c < F::C2; ++c) {
-    const cx<T> bc = tw_u[2 * fft3_out_index<F>(t, c, 0)];
+    const cx<T> bc = tw_u[2 * fft3_out_index<F>(to, c, 0)];
     static_for<F::R3>([&](auto mc) {
       constexpr int mp = decltype(mc)::value;
       v[c * F::R3 + mp] = cmul(rot<mp, 2 * F::R3, +1>(bc), v[c * F::R3 + mp]);
