@@ -583,7 +583,9 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   uint32_t cols[F::C1];
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
-  corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
+  // 32 points per thread: these kernels hold 4 waves per SIMD whatever their
+  // register count below 128, so the early twiddle request is free
+  corr_pre<F, MAP_MIRROR, G, T, TW, (F::P >= 32)>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
   const double S = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
@@ -645,7 +647,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   uint32_t cols[F::C1];
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
-  corr_pre<F, MAP_MIRROR, G, T, TW>(v, acc, cols, rW, rY, 0u, tw_u, 2u, 0u, t);
+  corr_pre<F, MAP_MIRROR, G, T, TW, true>(v, acc, cols, rW, rY, 0u, tw_u, 2u, 0u, t);
   const double S0 = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
 
   // The odd half derives its lane addresses from an opaque copy of the thread
