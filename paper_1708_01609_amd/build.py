@@ -35,6 +35,9 @@ def compile_command(out: str = LIB) -> list[str]:
         "-std=c++17",
         "-fPIC",
         "-shared",
+        # multiply-adds fused only within one source expression, so every
+        # kernel instantiation (dense, threshold, projection) rounds alike
+        "-ffp-contract=on",
         # packed FP32 VALU forms are kept out of every kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"),

@@ -114,19 +114,38 @@ __device__ __forceinline__ uint32_t fft3_col(int t, int c) {
 // thread loads row 1 and every eighth row (anchors) and walks a running
 // power w^i = w^(i-1) w between anchors, so each twiddle is at most seven
 // products from an exact table value and only a handful of registers stay
-// live.
-template <int R, int DIR, typename T>
-__device__ __forceinline__ void twiddle_rows(cx<T>* v, const cx<T>* __restrict__ tab, uint32_t stride, uint32_t e) {
+// live.  The anchors are requested (twiddle_load) ahead of the arithmetic
+// that precedes their use, so the wait for them finds them arrived.
+template <int R, typename T>
+struct Anchors {
+  static constexpr int NA = R > 1 ? 1 + (R - 1) / 8 : 1;  // row 1, rows 8, 16, ...
+  cx<T> a[NA];
+};
+
+template <int R, typename T>
+__device__ __forceinline__ Anchors<R, T> twiddle_load(const cx<T>* __restrict__ tab, uint32_t stride, uint32_t e) {
+  Anchors<R, T> w{};
   if constexpr (R > 1) {
     const rsrc_t rt = make_rsrc(tab, uint32_t(R) * stride * uint32_t(sizeof(cx<T>)));
     const uint32_t voff = e * uint32_t(sizeof(cx<T>));
-    cx<T> w1 = buf_load<cx<T>>(rt, voff, stride * uint32_t(sizeof(cx<T>)));
+    w.a[0] = buf_load<cx<T>>(rt, voff, stride * uint32_t(sizeof(cx<T>)));
+#pragma unroll
+    for (int k = 1; k < Anchors<R, T>::NA; ++k)
+      w.a[k] = buf_load<cx<T>>(rt, voff, uint32_t(8 * k) * stride * uint32_t(sizeof(cx<T>)));
+  }
+  return w;
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void twiddle_apply(cx<T>* v, const Anchors<R, T>& an) {
+  if constexpr (R > 1) {
+    cx<T> w1 = an.a[0];
     if constexpr (DIR < 0) w1.y = -w1.y;
     cx<T> w = w1;
 #pragma unroll
     for (int i = 1; i < R; ++i) {
       if (i % 8 == 0) {
-        w = buf_load<cx<T>>(rt, voff, uint32_t(i) * stride * uint32_t(sizeof(cx<T>)));
+        w = an.a[i / 8];
         if constexpr (DIR < 0) w.y = -w.y;
       } else if (i > 1) {
         w = cmul(w, w1);
@@ -142,8 +161,9 @@ template <class F, int DIR, typename T>
 __device__ __forceinline__ void fft3_pass1(cx<T>* v, const cx<T>* __restrict__ tw1, const uint32_t* cols) {
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
+    const Anchors<F::R1, T> an = twiddle_load<F::R1, T>(tw1, F::S1, cols[c]);
     dft<F::R1, DIR, T>(&v[c * F::R1]);
-    twiddle_rows<F::R1, DIR, T>(&v[c * F::R1], tw1, F::S1, cols[c]);
+    twiddle_apply<F::R1, DIR, T>(&v[c * F::R1], an);
     sched_fence();
   }
 }
@@ -186,21 +206,34 @@ __device__ __forceinline__ void fft3_ex1_read(cx<T>* v, const T* lds, int t) {
 }
 
 // Pass 2: DFT over j2 for every owned item, then w_S1^(m0*j1) (tw2 is
-// exp(+2 pi i m0 j1 / S1) as [m0][j1]).
+// exp(+2 pi i m0 j1 / S1) as [m0][j1]).  fft3_pass2_load requests the
+// anchors; callers issue it before exchange 1, whose barriers hide the wait.
+template <class F, typename T>
+struct Pass2Anchors {
+  Anchors<F::R2, T> an[F::C2];
+};
+template <class F, typename T>
+__device__ __forceinline__ Pass2Anchors<F, T> fft3_pass2_load(const cx<T>* __restrict__ tw2, int t) {
+  Pass2Anchors<F, T> p;
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) p.an[c] = twiddle_load<F::R2, T>(tw2, F::R3, uint32_t(t + F::NT * c) % F::R3);
+  return p;
+}
 template <class F, int DIR, typename T>
-__device__ __forceinline__ void fft3_pass2(cx<T>* v, const cx<T>* __restrict__ tw2, int t) {
+__device__ __forceinline__ void fft3_pass2(cx<T>* v, const Pass2Anchors<F, T>& p) {
 #pragma unroll
   for (int c = 0; c < F::C2; ++c) {
     dft<F::R2, DIR, T>(&v[c * F::R2]);
     sched_fence();
-    twiddle_rows<F::R2, DIR, T>(&v[c * F::R2], tw2, F::R3, uint32_t(t + F::NT * c) % F::R3);
+    twiddle_apply<F::R2, DIR, T>(&v[c * F::R2], p.an[c]);
     sched_fence();
   }
 }
+template <class F, int DIR, typename T>
+__device__ __forceinline__ void fft3_pass2(cx<T>* v, const cx<T>* __restrict__ tw2, int t) {
+  fft3_pass2<F, DIR, T>(v, fft3_pass2_load<F, T>(tw2, t));
+}
 
-// Exchange 2 (wave-local), both planes.  Thread lane l of group g holds
-// (n0, j1 = l % R3) with values over m0; afterwards it holds (n0, m0 = l % R2)
-// with values over j1.
 template <class F, typename T>
 __device__ __forceinline__ void fft3_ex2(cx<T>* v, T* lds, int t) {
   const int lane = t & 63, wave = t >> 6;

@@ -381,6 +381,7 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
     const double ws = wave_sum(acc);
     if ((t & 63) == 0) red[t >> 6] = ws;
   }
+  const Pass2Anchors<F, T> an2 = fft3_pass2_load<F, T>(tw2, t);
   fft3_ex1_write<F, 0>(v, lds, cols);
   lds_barrier();
   double S = 0.0;
@@ -395,7 +396,7 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
   lds_barrier();
   fft3_ex1_read<F, 1>(v, lds, t);
   lds_barrier();
-  fft3_pass2<F, +1>(v, tw2, t);
+  fft3_pass2<F, +1>(v, an2);
   fft3_ex2<F>(v, lds, t);
   fft3_pass3<F, +1>(v);
   return S;
