@@ -9,7 +9,7 @@ paper loads precomputed template transforms (Sec. 3.2, step (ii)); its build
 time is reported beside the step rate.
 
 Prints one JSON line.  With no flags: N = 1 GPU, workload C2 (N = 2^16,
-8192 one-second chirps, kappa = 5, FP32), 20 timed steps after 3 warmups;
+8192 one-second chirps, kappa = 5, FP32), 400 timed steps after 50 warmups (the clocks settle during the warmups);
 beside it the same with FP16-stored spectra, the batched form (C4: 64
 segments of 2^14..2^17 samples against 65,536 chirps in one graph-replayed
 job per step, autotuned kernels) and the serving form (C5: Poisson arrivals
@@ -34,9 +34,10 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
 # HBM bytes per corr_kernel launch on the C2 workload, from rocprofv3 FETCH_SIZE (x2, the
 # factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
-# for the kernel sources they were taken on (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
+# for the kernel sources and build flags they were taken on
+# (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "a4c2a4bab30a8f75": {"f32": 2.2012e9, "f32-w16f": 1.0900e9},
+    "1c107c65a406bace": {"f32": 2.1972e9, "f32-w16f": 1.0893e9},
 }
 
 
@@ -45,8 +46,11 @@ def kernel_source_hash() -> str:
     import hashlib
 
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1708_01609_amd", "csrc")
-    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+    pkg = os.path.join(ROOT, "paper_1708_01609_amd")
+    csrc = os.path.join(pkg, "csrc")
+    # the kernel sources and the build script (its compile flags)
+    for f in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))) + [
+            os.path.join(pkg, "build.py")]:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -71,8 +75,8 @@ def algorithmic_bytes(n: int, spec_bytes: int) -> float:
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=20)
-    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--steps", type=int, default=400)
+    p.add_argument("--warmup", type=int, default=50)
     p.add_argument("--workload", default="C2")
     p.add_argument("--precision", default="f32")
     p.add_argument("--no-cpu-baseline", action="store_true")
