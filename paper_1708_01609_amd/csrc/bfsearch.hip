@@ -342,9 +342,13 @@ struct JobBuffers {
   unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
   bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
   uint64_t tails_host_cap = 0;
-  // [0] job queued, [1]/[2] around the correlation kernels, [3] job done,
-  // [4] segment transforms done (orders the correlation stream after them)
+  // [0] job queued, [1]/[2] around the correlation kernels, [3] job done
+  // after the projection compaction, [4] segment transforms done (orders the
+  // correlation stream after them).  done = the event that completes the
+  // job: 3 when the compaction follows the kernels, else 2 (each record on
+  // the correlation stream costs a few microseconds between kernels).
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int done = 3;
   uint64_t bytes = 0;
   hipGraphExec_t gexec = nullptr;  // captured job body (graph plans)
   std::vector<uint64_t> gkey;      // the shape it was captured for
@@ -999,9 +1003,9 @@ bfs_status launch_graph(bfs_plan* p, JobBuffers* b, const Layout& L, hipStream_t
 // Queue a job.  Tail and projection jobs outside graph plans split over two
 // streams: the segment transforms on st, the correlation kernels on st's
 // paired stream after them (ev[4]), so st is free for the next job's
-// transforms while this job's correlations run; ev[3] marks the job done.
-// Graph plans and dense correlations keep the whole job on st.  *done_stream
-// is the stream ev[3] was recorded on.
+// transforms while this job's correlations run; ev[b->done] marks the job
+// done.  Graph plans and dense correlations keep the whole job on st.
+// *done_stream is the stream that event was recorded on.
 bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
                      hipStream_t st, hipStream_t* done_stream) {
   *done_stream = st;
@@ -1024,7 +1028,8 @@ bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, vo
     rs = enqueue_corr(p, b, L, false, nullptr, nullptr, cs, true);
     if (rs != BFS_OK) return rs;
   }
-  HIP_TRY(hipEventRecord(b->ev[3], *done_stream));
+  b->done = (p->project && !dense) ? 3 : 2;
+  if (b->done == 3) HIP_TRY(hipEventRecord(b->ev[3], *done_stream));
   return BFS_OK;
 }
 
@@ -1253,7 +1258,7 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
   if (p->project) return BFS_ERR_INVALID_ARG;
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(hipEventSynchronize(b->ev[3]));
+  HIP_TRY(hipEventSynchronize(b->ev[b->done]));
   HIP_TRY(read_counters(p, b));
   const unsigned long long count = *b->count_host;
   const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
@@ -1290,7 +1295,7 @@ bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t ca
   if (!p->project) return BFS_ERR_INVALID_ARG;
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(hipEventSynchronize(b->ev[3]));
+  HIP_TRY(hipEventSynchronize(b->ev[b->done]));
   HIP_TRY(read_counters(p, b));
   const unsigned long long count = b->count_host[1];  // <= the number of lags, the list's size
   std::vector<unsigned long long> list(2 * count);
@@ -1330,7 +1335,7 @@ bfs_status bfsearch_fetch_sigma(bfs_job* j, double* out_host) {
   if (!j || !out_host) return BFS_ERR_INVALID_ARG;
   bfs_plan* p = j->plan;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(hipStreamWaitEvent(p->copy_stream, j->buf->ev[3], 0));
+  HIP_TRY(hipStreamWaitEvent(p->copy_stream, j->buf->ev[j->buf->done], 0));
   HIP_TRY(hipMemcpyAsync(out_host, j->buf->sigma, uint64_t(j->S) * p->K * sizeof(double), hipMemcpyDeviceToHost,
                          p->copy_stream));
   HIP_TRY(hipStreamSynchronize(p->copy_stream));
@@ -1339,15 +1344,15 @@ bfs_status bfsearch_fetch_sigma(bfs_job* j, double* out_host) {
 
 bfs_status bfsearch_job_timing(bfs_job* j, float* corr_ms, float* total_ms) {
   if (!j || !corr_ms || !total_ms) return BFS_ERR_INVALID_ARG;
-  HIP_TRY(hipEventSynchronize(j->buf->ev[3]));
+  HIP_TRY(hipEventSynchronize(j->buf->ev[j->buf->done]));
   HIP_TRY(hipEventElapsedTime(corr_ms, j->buf->ev[1], j->buf->ev[2]));
-  HIP_TRY(hipEventElapsedTime(total_ms, j->buf->ev[0], j->buf->ev[3]));
+  HIP_TRY(hipEventElapsedTime(total_ms, j->buf->ev[0], j->buf->ev[j->buf->done]));
   return BFS_OK;
 }
 
 bfs_status bfsearch_job_poll(bfs_job* j, int* done) {
   if (!j || !done) return BFS_ERR_INVALID_ARG;
-  const hipError_t e = hipEventQuery(j->buf->ev[3]);
+  const hipError_t e = hipEventQuery(j->buf->ev[j->buf->done]);
   if (e == hipSuccess) {
     *done = 1;
     return BFS_OK;
@@ -1372,7 +1377,7 @@ bfs_status bfsearch_plan_job_bytes(const bfs_plan* p, const uint32_t* seg_length
 bfs_status bfsearch_job_release(bfs_job* j) {
   if (!j) return BFS_ERR_INVALID_ARG;
   // buffers may be reused by the next filter call: wait for this job's kernels
-  (void)hipEventSynchronize(j->buf->ev[3]);
+  (void)hipEventSynchronize(j->buf->ev[j->buf->done]);
   put_job_buffers(j->plan, j->buf);
   delete j;
   return BFS_OK;
