@@ -197,7 +197,8 @@ bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
  * Streams: the job starts after the work queued on hip_stream before the
  * call.  Outside BFS_PLAN_GRAPH plans, the segment transforms run on
  * hip_stream and the fused kernels on an internal stream of the plan paired
- * with hip_stream (created on first use, destroyed with the plan), queued
+ * with hip_stream (created on first use, at most 16 per plan with later
+ * caller streams sharing them, destroyed with the plan), queued
  * after those transforms; so the next call's transforms overlap this call's
  * correlations, and work queued later on hip_stream is ordered after the
  * transforms only.  BFS_PLAN_GRAPH plans replay the whole job on hip_stream.

@@ -388,8 +388,11 @@ struct bfs_plan {
   // Correlation stream paired with each caller stream that queued jobs: a
   // job's segment transforms run on the caller's stream, its correlation
   // kernels on the paired stream, so the next job's transforms overlap them.
+  // At most MAX_CORR_STREAMS are created; later caller streams share them
+  // (still correct: their fused kernels then run one after another).
   std::mutex stream_mu;
-  std::vector<std::pair<hipStream_t, hipStream_t>> corr_streams;
+  std::vector<std::pair<hipStream_t, hipStream_t>> corr_streams;  // caller stream -> paired stream
+  std::vector<hipStream_t> owned_streams;
   std::mutex mu;
   std::vector<JobBuffers*> pool;
   uint64_t live_job_bytes = 0;
@@ -458,7 +461,7 @@ void free_plan(bfs_plan* p) {
   }
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
-  for (auto& cs : p->corr_streams) (void)hipStreamDestroy(cs.second);
+  for (hipStream_t cs : p->owned_streams) (void)hipStreamDestroy(cs);
   delete p;
 }
 
@@ -943,6 +946,7 @@ bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
 
 // The correlation stream paired with the caller's stream st (created on first
 // use, non-blocking, default priority; destroyed with the plan).
+constexpr size_t MAX_CORR_STREAMS = 16;
 bfs_status corr_stream(bfs_plan* p, hipStream_t st, hipStream_t* out) {
   std::lock_guard<std::mutex> lk(p->stream_mu);
   for (const auto& e : p->corr_streams)
@@ -951,7 +955,12 @@ bfs_status corr_stream(bfs_plan* p, hipStream_t st, hipStream_t* out) {
       return BFS_OK;
     }
   hipStream_t cs = nullptr;
-  HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  if (p->owned_streams.size() < MAX_CORR_STREAMS) {
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    p->owned_streams.push_back(cs);
+  } else {
+    cs = p->owned_streams[p->corr_streams.size() % MAX_CORR_STREAMS];
+  }
   p->corr_streams.emplace_back(st, cs);
   *out = cs;
   return BFS_OK;
