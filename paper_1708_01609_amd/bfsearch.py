@@ -250,7 +250,10 @@ class Plan:
         return y
 
     def filter(self, y, lengths=None, offsets=None, stream=None) -> "Job":
-        """Queue the hot path on `stream` (torch stream; default: current) and return the job.
+        """Queue the hot path after the work on `stream` (torch stream; default: current) and
+        return the job.  The segment transforms run on `stream`, the fused kernels on the
+        plan's stream paired with it (graph plans: all on `stream`); wait through the job
+        (fetch, done, timing, release), not through `stream`.
 
         y: [S, n] for segments of the plan's largest length; or, with `lengths` (one power of
         two in [n_min, n] per segment), a flat tensor holding the segments back to back (or at
@@ -371,7 +374,8 @@ class Job:
         return out
 
     def timing(self) -> tuple[float, float]:
-        """(fused correlation kernel ms, whole job ms) from HIP events on the job's stream."""
+        """(fused correlation kernel ms, whole job ms) from HIP events on the streams the job's
+        kernels run on."""
         c, t = ctypes.c_float(), ctypes.c_float()
         _check(_lib.bfsearch_job_timing(self._h, ctypes.byref(c), ctypes.byref(t)), "bfsearch_job_timing")
         return c.value, t.value
