@@ -13,8 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libbfsearch.so")
-SOURCES = [os.path.join(CSRC, "bfsearch.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("bfs_device.h", "bfs_fft3.h", "bfs_kernels.h")] + [
+SOURCES = [os.path.join(CSRC, "bfsearch.hip"), os.path.join(CSRC, "bfs_tail_sort.hip")]
+HEADERS = [os.path.join(CSRC, f) for f in ("bfs_device.h", "bfs_fft3.h", "bfs_kernels.h", "bfs_tail_sort.h")] + [
     os.path.join(ROOT, "include", "bfsearch.h")
 ]
 ARCH = "gfx950"

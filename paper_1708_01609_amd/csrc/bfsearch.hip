@@ -16,10 +16,12 @@
 
 #include "bfsearch.h"
 #include "bfs_kernels.h"
+#include "bfs_tail_sort.h"
 
 using namespace bfs;
 
 static_assert(sizeof(tail_rec) == sizeof(bfs_tail), "tail record layout");
+static_assert(sizeof(tail_sort_rec) == sizeof(bfs_tail), "tail record layout");
 
 namespace {
 
@@ -342,6 +344,9 @@ struct JobBuffers {
   unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
   bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
   uint64_t tails_host_cap = 0;
+  void* sorted = nullptr;  // device: sorted tail records [sort_cap], then the sort's work area
+  uint64_t sort_cap = 0;
+  uint64_t sort_bytes = 0;
   // [0] job queued, [1]/[2] around the correlation kernels, [3] job done
   // after the projection compaction, [4] segment transforms done (orders the
   // correlation stream after them).  done = the event that completes the
@@ -445,6 +450,7 @@ void free_job_buffers(JobBuffers* b) {
   if (b->meta_host) (void)hipHostFree(b->meta_host);
   if (b->count_host) (void)hipHostFree(b->count_host);
   if (b->tails_host) (void)hipHostFree(b->tails_host);
+  if (b->sorted) (void)hipFree(b->sorted);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   for (auto& e : b->ev)
     if (e) (void)hipEventDestroy(e);
@@ -1051,6 +1057,41 @@ hipError_t read_counters(bfs_plan* p, JobBuffers* b) {
   return e;
 }
 
+// Fetches of at least DEVICE_SORT_MIN tails are ordered on the device.
+constexpr uint64_t DEVICE_SORT_MIN = 1u << 15;
+
+uint64_t sort_out_bytes(uint64_t n) { return (n * sizeof(bfs_tail) + 255) & ~uint64_t(255); }
+
+// Make b's device sort area hold n records (grown to at most the tail
+// capacity, kept with the buffers).  Its bytes count against the plan's HBM
+// budget as part of the job; false (and the host sort) when they do not fit
+// or the allocation fails.
+bool ensure_sort(bfs_plan* p, JobBuffers* b, uint64_t n) {
+  if (b->sorted && b->sort_cap >= n) return true;
+  const uint64_t want = std::min<uint64_t>(p->cap, std::max<uint64_t>(n, 2 * b->sort_cap));
+  const size_t work = tail_sort_work_bytes(want);
+  if (!work) return false;
+  const uint64_t bytes = sort_out_bytes(want) + work;
+  std::lock_guard<std::mutex> lk(p->mu);
+  if (p->plan_bytes + p->live_job_bytes - b->sort_bytes + bytes > p->budget) return false;
+  if (b->sorted) (void)hipFree(b->sorted);
+  p->live_job_bytes -= b->sort_bytes;
+  b->bytes -= b->sort_bytes;
+  b->sorted = nullptr;
+  b->sort_cap = 0;
+  b->sort_bytes = 0;
+  if (hipMalloc(&b->sorted, bytes) != hipSuccess) {
+    b->sorted = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  b->sort_cap = want;
+  b->sort_bytes = bytes;
+  b->bytes += bytes;
+  p->live_job_bytes += bytes;
+  return true;
+}
+
 // Tails in (segment, template_id, lag) order.  The device writes them in
 // whatever order the atomics hand out slots; sorting makes the result
 // deterministic.  LSD radix sort (16-bit digits) of the packed key
@@ -1285,11 +1326,29 @@ bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacit
     b->tails_host_cap = want;
   }
   bfs_tail* tmp = b->tails_host;
-  if (on_dev) {
-    HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
-    HIP_TRY(hipStreamSynchronize(p->copy_stream));
+  bool sorted = false;
+  if (on_dev >= DEVICE_SORT_MIN && p->K < (1u << 31) && p->n_max <= (1u << 17) && ensure_sort(p, b, on_dev)) {
+    // order on the device, then one copy of the sorted records
+    const uint32_t end_bit = j->S > 1 ? 48u + uint32_t(32 - __builtin_clz(j->S - 1)) : 48u;
+    auto* out = static_cast<tail_sort_rec*>(b->sorted);
+    char* work = static_cast<char*>(b->sorted) + sort_out_bytes(b->sort_cap);
+    if (tail_sort(reinterpret_cast<const tail_sort_rec*>(b->tails), on_dev, end_bit, work,
+                  b->sort_bytes - sort_out_bytes(b->sort_cap), out, p->copy_stream) == hipSuccess) {
+      HIP_TRY(hipMemcpyAsync(tmp, out, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+      sorted = true;
+    } else {
+      (void)hipGetLastError();
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+    }
   }
-  sort_tails(tmp, on_dev);
+  if (!sorted) {
+    if (on_dev) {
+      HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+    }
+    sort_tails(tmp, on_dev);
+  }
   const uint64_t nw = std::min<uint64_t>(on_dev, capacity);
   if (nw) std::memcpy(out_host, tmp, nw * sizeof(bfs_tail));
   *n_written = nw;
