@@ -560,3 +560,22 @@ def test_many_tails_come_back_complete_and_sorted(bfs):
     assert np.array_equal(tails["template"], np.tile(np.repeat(np.arange(K), n), S))
     assert np.array_equal(tails["lag"], np.tile(np.arange(n), S * K))
     assert np.array_equal(tails["rho"].astype(np.float32), rho.reshape(-1))
+
+
+def test_device_and_host_tail_sorts_agree(bfs):
+    # 61,440 tails are ordered on the device; under an HBM budget with no room for the
+    # device sort's work area the same fetch falls back to the host sort: same records
+    n, S, K = 4096, 3, 5
+    rng = np.random.default_rng(16)
+    ys = _dev(rng.standard_normal((S, n)).astype(np.float32), np.float32)
+    temps = rng.standard_normal((K, 300))
+    kw = dict(kappa=0.0, templates=temps, precision="f32", tail_capacity=S * K * n)
+    with bfs.Plan(n, 4096.0, **kw) as plan:
+        need = plan.plan_bytes + plan.job_bytes([n] * S)
+        with plan.filter(ys) as job:
+            dev_sorted, total = job.fetch_tails()
+    with bfs.Plan(n, 4096.0, hbm_budget_bytes=need + (256 << 10), **kw) as plan:
+        with plan.filter(ys) as job:
+            host_sorted, total2 = job.fetch_tails()
+    assert total == total2 == S * K * n
+    assert np.array_equal(dev_sorted, host_sorted)
