@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # for the kernel sources and build flags they were taken on
 # (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "eeba745df8067a20": {"f32": 2.1948e9, "f32-w16f": 1.0895e9},
+    "a05babbe0536b173": {"f32": 2.2065e+09, "f32-w16f": 1.0890e+09},
 }
 
 
