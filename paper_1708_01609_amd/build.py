@@ -27,35 +27,57 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def compile_command(out: str = LIB) -> list[str]:
-    return [
-        hipcc(),
-        f"--offload-arch={ARCH}",
-        "-O3",
-        "-std=c++17",
-        "-fPIC",
-        "-shared",
-        # multiply-adds fused only within one source expression, so every
-        # kernel instantiation (dense, threshold, projection) rounds alike
-        "-ffp-contract=on",
-        # packed FP32 VALU forms are kept out of every kernel
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-I", os.path.join(ROOT, "include"),
-        "-o", out,
-        *SOURCES,
-    ]
+FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    # multiply-adds fused only within one source expression, so every
+    # kernel instantiation (dense, threshold, projection) rounds alike
+    "-ffp-contract=on",
+    # packed FP32 VALU forms are kept out of every kernel
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-I", os.path.join(ROOT, "include"),
+]
+OBJDIR = os.path.join(HERE, "_build")
+
+
+def compile_commands() -> list[list[str]]:
+    """One hipcc -c per source (they compile in parallel), objects under _build/."""
+    return [[hipcc(), *FLAGS, "-c", "-o", os.path.join(OBJDIR, os.path.basename(src) + ".o"), src]
+            for src in SOURCES]
+
+
+def link_command(out: str = LIB) -> list[str]:
+    return [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out,
+            *[os.path.join(OBJDIR, os.path.basename(src) + ".o") for src in SOURCES]]
 
 
 def build(verbose: bool = False) -> str:
     """Compile the library (always; this is the build check) and return its path."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    cmds = compile_commands()
+    if verbose:
+        for c in cmds:
+            print(" ".join(c), flush=True)
+    procs = [subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True) for c in cmds]
+    failed = []
+    for c, pr in zip(cmds, procs):
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            failed.append((c, pr.returncode, out))
+    if failed:
+        for c, rc, out in failed:
+            sys.stderr.write(" ".join(c) + "\n" + out)
+        raise RuntimeError(f"hipcc failed with exit code {failed[0][1]}")
     tmp = LIB + ".tmp"
-    cmd = compile_command(tmp)
+    cmd = link_command(tmp)
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError(f"hipcc failed with exit code {res.returncode}")
+        raise RuntimeError(f"hipcc link failed with exit code {res.returncode}")
     os.replace(tmp, LIB)
     return LIB
 
