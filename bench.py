@@ -306,7 +306,8 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
-              "(template- or segment-parallel sharding needs no exchange; see DESIGN.md)", file=sys.stderr)
+              "(it would shard by templates or segments, one resident bank slice per GPU, with no "
+              "exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
