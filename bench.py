@@ -305,7 +305,7 @@ def cpu_baseline(w, y, n_templates, min_seconds=10.0, max_passes=32):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+        print("bench.py: runs on one GPU only; multi-GPU runs are not supported "
               "(it would shard by templates or segments, one resident bank slice per GPU, with no "
               "exchange between GPUs)", file=sys.stderr)
         sys.exit(2)
