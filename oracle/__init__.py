@@ -17,8 +17,11 @@ from .bfsearch_oracle import (
     threshold_tails,
     search,
     max_projection,
+    pair_segments,
+    coincidences,
     TAIL_DTYPE,
     PEAK_DTYPE,
+    COINC_DTYPE,
 )
 
 __all__ = [
@@ -34,6 +37,9 @@ __all__ = [
     "threshold_tails",
     "search",
     "max_projection",
+    "pair_segments",
+    "coincidences",
     "TAIL_DTYPE",
     "PEAK_DTYPE",
+    "COINC_DTYPE",
 ]

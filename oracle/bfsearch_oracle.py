@@ -31,6 +31,13 @@ What it computes, per segment y (length N) and template w (length L <= N):
   as the signed rho / sigma with its template.  The paper's update of the
   projection array is racy (its text says so); here equal significances go to
   the lowest template id, so the result is unique (see max_projection).
+* two detectors (Sec. 3.2 step (i) processes H1 and L1 segments as pairs;
+  Sec. 5 and Table 3): the two channels of a pair are time-aligned segments
+  of equal length, searched like any other segment (pair p's channels are
+  segments 2p and 2p + 1).  A coincidence is a lag at which both channels
+  carry a projected hit and the initial frequencies of the two winning
+  templates differ by less than Delta (the "simultaneous hits with frequency
+  pairs within Delta = 50 Hz" of Sec. 5), see coincidences.
 
 Templates (Sec. 2 uses chirps from a spin-down model that the paper does not
 give; linear chirps stand in): w[m] = h[m] cos(2 pi (f0 t + fdot t^2 / 2)),
@@ -46,6 +53,8 @@ import scipy.fft as sfft
 
 TAIL_DTYPE = np.dtype([("segment", np.uint32), ("template", np.uint32), ("lag", np.uint32), ("rho", np.float64)])
 PEAK_DTYPE = np.dtype([("segment", np.uint32), ("lag", np.uint32), ("template", np.uint32), ("snr", np.float64)])
+COINC_DTYPE = np.dtype([("pair", np.uint32), ("lag", np.uint32), ("template_a", np.uint32), ("template_b", np.uint32),
+                        ("snr_a", np.float64), ("snr_b", np.float64)])
 
 
 def _workers() -> int:
@@ -72,7 +81,7 @@ def chirp_template(f0: float, fdot: float, length: int, fs: float,
     Stand-in for the time-sliced spin-down chirps of Sec. 2; f0 is the
     initial frequency (the quantity Table 3 lists per hit).  Sampled as
     written, aliasing included; unit energy when normalize is set.
-    symmetric: the time-symmetric template of the paper's banks (Fig. 1
+    symmetric: the time-symmetric template of the paper's banks (Fig. 2
     caption), the chirp plus its own time reversal, x[m] + x[L-1-m], which
     matches ascending and descending chirps alike; normalised after the sum.
     """
@@ -169,7 +178,7 @@ def threshold_tails(rho: np.ndarray, sigma: float, kappa: float, kappa_hi: float
     """Lags n with |rho_n| > kappa * sigma (Eq. (9) on the absolute value), ascending.
 
     kappa_hi > 0 keeps a finite band instead, kappa sigma < |rho_n| < kappa_hi sigma: the
-    generalisation the paper proposes for deep searches (Sec. 4, last paragraphs)."""
+    generalisation the paper proposes for very deep searches (Sec. 5)."""
     if not sigma > 0:
         return np.zeros(0, dtype=np.int64)
     keep = np.abs(rho) > kappa * sigma
@@ -255,3 +264,41 @@ def max_projection(tails: np.ndarray, sigma: np.ndarray) -> np.ndarray:
     for i, ((s, n), (v, j, r)) in enumerate(sorted(best.items())):
         out[i] = (s, n, j, r / float(sigma[s, j]))
     return out
+
+
+# -------------------------------------------------------------- two detectors --
+
+def pair_segments(first, second):
+    """Interleave the channels of detector pairs: pair p's first channel becomes segment 2p, its
+    second channel segment 2p + 1 (equal lengths within a pair, Sec. 3.2 step (i))."""
+    if len(first) != len(second):
+        raise ValueError("every pair needs both channels")
+    out = []
+    for a, b in zip(first, second):
+        if len(a) != len(b):
+            raise ValueError("the channels of a pair must have equal lengths")
+        out += [a, b]
+    return out
+
+
+def coincidences(proj: np.ndarray, f0: np.ndarray, delta: float) -> np.ndarray:
+    """Simultaneous hits of detector pairs with close template frequencies (Sec. 5, Table 3).
+
+    proj: PEAK_DTYPE per-lag max projection over interleaved pair segments (max_projection of
+    the tails of pair_segments(...)); f0: initial frequency (Hz) of every template, which is the
+    frequency the output table lists per hit; delta: Hz.  Pair p has a coincidence at lag n
+    when both its channels (segments 2p, 2p + 1) carry a projected hit at n and the winning
+    templates' initial frequencies satisfy |f_a - f_b| < delta.  Returns COINC_DTYPE records
+    sorted by (pair, lag), with each channel's template and signed rho / sigma.
+    """
+    f0 = np.asarray(f0, dtype=np.float64)
+    first, second = {}, {}
+    for s, n, j, v in zip(proj["segment"], proj["lag"], proj["template"], proj["snr"]):
+        (first if int(s) % 2 == 0 else second)[(int(s) // 2, int(n))] = (int(j), float(v))
+    rows = []
+    for key in sorted(first.keys() & second.keys()):
+        ja, va = first[key]
+        jb, vb = second[key]
+        if abs(f0[ja] - f0[jb]) < delta:
+            rows.append((key[0], key[1], ja, jb, va, vb))
+    return np.array(rows, dtype=COINC_DTYPE) if rows else np.zeros(0, dtype=COINC_DTYPE)

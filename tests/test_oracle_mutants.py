@@ -37,6 +37,12 @@ MUTANTS = {
     "projection_raw_rho": ("v = abs(r) / float(sigma[s, j])", "v = abs(r)"),
     "projection_signed": ("v = abs(r) / float(sigma[s, j])", "v = r / float(sigma[s, j])"),
     "projection_highest_id": ("if v > bv or (v == bv and j < bj):", "if v > bv or (v == bv and j > bj):"),
+    "coinc_window_inclusive": ("if abs(f0[ja] - f0[jb]) < delta:", "if abs(f0[ja] - f0[jb]) <= delta:"),
+    "coinc_no_abs": ("if abs(f0[ja] - f0[jb]) < delta:", "if f0[ja] - f0[jb] < delta:"),
+    "coinc_template_ids": ("if abs(f0[ja] - f0[jb]) < delta:", "if abs(ja - jb) < delta:"),
+    "coinc_pair_from_segment": ("(first if int(s) % 2 == 0 else second)[(int(s) // 2, int(n))] = (int(j), float(v))",
+                                "(first if int(s) % 2 == 0 else second)[(int(s), int(n))] = (int(j), float(v))"),
+    "coinc_snr_swapped": ("rows.append((key[0], key[1], ja, jb, va, vb))", "rows.append((key[0], key[1], ja, jb, vb, va))"),
 }
 
 PIN_TESTS = [
@@ -57,6 +63,10 @@ PIN_TESTS = [
     (pins.test_max_projection_ties_scale_and_sign, [()]),
     (pins.test_time_symmetric_template_mirrors_correlation_of_reversed_data, [()]),
     (pins.test_band_threshold_keeps_only_the_band, [()]),
+    (pins.test_coincidences_of_table3_rows, [(50.0, [17713196, 17713197, 17713198, 17713199]),
+                                             (5.0, [17713197, 17713198, 17713199]), (1.0, [])]),
+    (pins.test_coincidences_of_identical_channels_are_every_projected_lag, [()]),
+    (pins.test_coincidences_swap_symmetry_and_monotone_window, [()]),
 ]
 
 

@@ -6,6 +6,7 @@ Gaussian expectation.  The comment on each test names the plausible mistake
 it would catch.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -336,3 +337,116 @@ def test_band_threshold_keeps_only_the_band():
     assert oracle.threshold_tails(edges, 1.0, 2.0, 2.5).tolist() == [3, 4]
     out = oracle.search([rho[:512]], [np.ones(1)], 1.5, kappa_hi=2.0)
     assert all(1.5 < abs(v) / out["sigma"][0, 0] < 2.0 for v in out["tails"]["rho"])
+
+
+# ------------------------------------------------------------------ two detectors --
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _table3_projection():
+    """The rows of Table 3 as a projection of pair 0 (H1 = segment 0, L1 = segment 1): lags are
+    offsets from the first printed row, each distinct printed frequency is one template."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "table3_b161_rows.txt"), comments="#")
+    freqs = sorted({f for f in np.concatenate([rows[:, 3], rows[:, 4]]) if f > 0})
+    tid = {f: i for i, f in enumerate(freqs)}
+    recs = []
+    for off, ra, rb, fa, fb in rows:
+        lag = int(off - rows[0, 0])
+        if ra > 0:
+            recs.append((0, lag, tid[fa], ra / 1000.0))
+        if rb > 0:
+            recs.append((1, lag, tid[fb], rb / 1000.0))
+    proj = np.array(recs, dtype=oracle.PEAK_DTYPE)
+    return rows, proj, np.array(freqs, dtype=np.float64)
+
+
+@pytest.mark.parametrize("delta,offsets", [
+    (50.0, [17713196, 17713197, 17713198, 17713199]),  # the four simultaneous hits, all within 50 Hz
+    (5.0, [17713197, 17713198, 17713199]),             # 497 vs 489 Hz is 8 Hz apart
+    (1.5, [17713197, 17713198]),                       # 563 vs 565 Hz is 2 Hz apart
+    (1.0, []),                                         # 1 Hz apart is not strictly within 1 Hz
+])
+def test_coincidences_of_table3_rows(delta, offsets):
+    # pinned by the paper's printed output: the simultaneous hits of Table 3 are the rows with a
+    # hit in both detectors; the frequency window keeps pairs strictly closer than delta.
+    # catches: a missing abs, <= for <, comparing template ids instead of frequencies, a lag
+    # or pair taken from one channel only
+    rows, proj, f0 = _table3_projection()
+    got = oracle.coincidences(proj, f0, delta)
+    assert [int(rows[0, 0]) + int(n) for n in got["lag"]] == offsets
+    assert np.all(got["pair"] == 0)
+    by_off = {int(r[0]): r for r in rows}
+    for c in got:
+        r = by_off[int(rows[0, 0]) + int(c["lag"])]
+        assert f0[c["template_a"]] == r[3] and f0[c["template_b"]] == r[4]
+        assert c["snr_a"] == r[1] / 1000.0 and c["snr_b"] == r[2] / 1000.0
+
+
+def _pair_search(n_pairs=2, n=2048, same=False, seed=40):
+    w = get_workload("C1")
+    f0, fd, tau = oracle.grid_params(6, 4, (400.0, 1800.0), (-200.0, 200.0), (0.125,))
+    bank = oracle.template_bank(f0, fd, tau, w.fs)
+    a = [bandlimited_noise(n, w.fs, seeded_rng(9, 0, p, "noise")) for p in range(n_pairs)]
+    b = a if same else [bandlimited_noise(n, w.fs, seeded_rng(9, 1, p, "noise")) for p in range(n_pairs)]
+    segs = oracle.pair_segments(a, b)
+    out = oracle.search(segs, bank, 2.5)
+    return oracle.max_projection(out["tails"], out["sigma"]), f0
+
+
+def test_coincidences_of_identical_channels_are_every_projected_lag():
+    # catches: a channel or pair index taken from the wrong segment, strict vs loose window
+    proj, f0 = _pair_search(same=True)
+    got = oracle.coincidences(proj, f0, 50.0)
+    first = proj[proj["segment"] % 2 == 0]
+    assert len(got) == len(first) > 0
+    assert np.array_equal(got["pair"], first["segment"] // 2) and np.array_equal(got["lag"], first["lag"])
+    assert np.array_equal(got["template_a"], got["template_b"]) and np.array_equal(got["snr_a"], got["snr_b"])
+    assert len(oracle.coincidences(proj, f0, 0.0)) == 0  # |f_a - f_b| = 0 is not < 0
+
+
+def test_coincidences_swap_symmetry_and_monotone_window():
+    proj, f0 = _pair_search()
+    swapped = proj.copy()
+    swapped["segment"] = swapped["segment"] ^ 1
+    wide = oracle.coincidences(proj, f0, np.inf)
+    # an unbounded window leaves the simultaneous hits: lags present in both channels
+    both = {(int(s) // 2, int(n)) for s, n in zip(proj["segment"], proj["lag"]) if s % 2 == 0} & \
+           {(int(s) // 2, int(n)) for s, n in zip(proj["segment"], proj["lag"]) if s % 2 == 1}
+    assert {(int(p), int(n)) for p, n in zip(wide["pair"], wide["lag"])} == both and len(both) > 0
+    prev = None
+    for delta in (0.0, 100.0, 300.0, 1000.0, np.inf):
+        got = oracle.coincidences(proj, f0, delta)
+        sw = oracle.coincidences(swapped, f0, delta)
+        assert np.array_equal(got["lag"], sw["lag"]) and np.array_equal(got["template_a"], sw["template_b"])
+        assert np.array_equal(got["snr_a"], sw["snr_b"])
+        keys = {(int(p), int(n)) for p, n in zip(got["pair"], got["lag"])}
+        assert prev is None or prev <= keys
+        assert all(abs(f0[a] - f0[b]) < delta for a, b in zip(got["template_a"], got["template_b"]))
+        prev = keys
+
+
+def test_chirp_in_both_channels_gives_coincidences_at_its_offset():
+    # one chirp injected at the same offset into two independent noise channels (Sec. 5: an
+    # injection seen in both detectors): coincidences appear around the injected offset, and
+    # there the winning templates of both channels are the injected chirp's neighbours in f0
+    fs, n, L, off = 4096.0, 8192, 1024, 3000
+    f0, fd, tau = oracle.grid_params(8, 8, (400.0, 1800.0), (-200.0, 200.0), (0.25,))
+    bank = oracle.template_bank(f0, fd, tau, fs)
+    s = 16.0 * unit_hann_chirp(600.0, 0.0, L, fs)
+    a = bandlimited_noise(n, fs, seeded_rng(9, 0, 7, "noise"))
+    b = bandlimited_noise(n, fs, seeded_rng(9, 1, 7, "noise"))
+    a[off:off + L] += s
+    b[off:off + L] += s
+    out = oracle.search(oracle.pair_segments([a], [b]), bank, 4.0)
+    proj = oracle.max_projection(out["tails"], out["sigma"])
+    got = oracle.coincidences(proj, f0, 50.0)
+    near = got[np.abs(got["lag"].astype(np.int64) - off) <= 64]
+    assert len(near) > 0
+    assert np.all(np.abs(f0[near["template_a"]] - 600.0) < 100.0)
+    assert np.all(np.abs(f0[near["template_b"]] - 600.0) < 100.0)
+    # no chirp in the second channel: far fewer coincidences near the offset
+    b2 = bandlimited_noise(n, fs, seeded_rng(9, 1, 7, "noise"))
+    out2 = oracle.search(oracle.pair_segments([a], [b2]), bank, 4.0)
+    got2 = oracle.coincidences(oracle.max_projection(out2["tails"], out2["sigma"]), f0, 50.0)
+    assert len(got2[np.abs(got2["lag"].astype(np.int64) - off) <= 64]) < len(near)
