@@ -73,7 +73,7 @@ typedef enum {
 #define BFS_PLAN_SYMMETRIC 8u /* grid templates symmetric in time: the chirp
                                  plus its time reversal, x[m] + x[L-1-m],
                                  normalised after the sum (the paper's bank
-                                 shape, Fig. 1 caption), for ascending and
+                                 shape, Fig. 2 caption), for ascending and
                                  descending chirps alike */
 
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
@@ -139,7 +139,7 @@ typedef struct {
   double kappa_hi;              /* 0: tails are |rho| > kappa sigma; > kappa: a
                                    finite band kappa sigma < |rho| < kappa_hi sigma
                                    (the deep-search generalisation of Eq. 9 the
-                                   paper proposes in Sec. 4) */
+                                   paper proposes in Sec. 5) */
 } bfs_plan_desc;
 
 /* Read-only facts about a plan. */
@@ -150,6 +150,9 @@ typedef struct {
   uint64_t plan_bytes;          /* all device memory held by the plan */
   uint32_t precision;
   uint32_t n_min;               /* smallest accepted segment length */
+  uint64_t held_bytes;          /* device bytes the plan holds now: plan memory,
+                                   live jobs' buffers and released buffer sets kept
+                                   for reuse; never above the HBM budget */
 } bfs_plan_info;
 
 /* The fused kernel a plan runs at one segment length. */
@@ -208,8 +211,11 @@ bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* se
                            const uint32_t* seg_lengths, uint32_t n_segments, void* hip_stream,
                            bfs_job** out);
 
-/* Wait for the job, copy its tails to out_host sorted by (segment,
- * template_id, lag), and report counts.
+/* Gather the tails to the host (Sec. 3.3: only the hits above threshold
+ * cross to the host, never the correlation output itself; this is the
+ * paper's mode that gathers every hit, without max selection).  Waits for
+ * the job, copies its tails to out_host sorted by (segment, template_id,
+ * lag), and reports counts.
  *   capacity: slots in out_host; *n_written <= capacity; *n_total = exact
  *   number of tails the kernels found.  Returns BFS_ERR_TAIL_OVERFLOW when
  *   *n_total exceeds capacity or the plan's tail_capacity; the records then
@@ -271,6 +277,16 @@ bfs_status bfsearch_plan_kernel_info(const bfs_plan* plan, uint32_t n, bfs_kerne
  * kernels finish. */
 bfs_status bfsearch_correlate_dense(bfs_plan* plan, const void* y_dev, uint32_t seg_len, uint32_t n_segments,
                                     void* rho_dev, double* sigma_dev, void* hip_stream);
+
+/* Diagnostic: as bfsearch_correlate_dense for the templates first..first+count-1
+ * only (the parity checks of large banks take them block by block).
+ * rho_dev: [n_segments][count][seg_len] of the plan's sample type;
+ * sigma_dev: [n_segments][count] doubles (may be NULL).  BFS_ERR_INVALID_ARG
+ * when the range leaves the bank or count is 0.  Returns after the kernels
+ * finish. */
+bfs_status bfsearch_correlate_dense_range(bfs_plan* plan, const void* y_dev, uint32_t seg_len, uint32_t n_segments,
+                                          uint32_t first, uint32_t count, void* rho_dev, double* sigma_dev,
+                                          void* hip_stream);
 
 /* Diagnostic: template spectra W_j[k], k = 0..n/2, at segment length n (0 =
  * the plan's largest), as interleaved FP64 complex into caller device memory

@@ -92,6 +92,7 @@ class PlanInfo(ctypes.Structure):
         ("plan_bytes", ctypes.c_uint64),
         ("precision", ctypes.c_uint32),
         ("n_min", ctypes.c_uint32),
+        ("held_bytes", ctypes.c_uint64),
     ]
 
 
@@ -114,6 +115,7 @@ def _load() -> ctypes.CDLL:
         "bfsearch_plan_get_info": [vp, ctypes.POINTER(PlanInfo)],
         "bfsearch_plan_kernel_info": [vp, u32, ctypes.POINTER(KernelInfo)],
         "bfsearch_correlate_dense": [vp, vp, u32, u32, vp, vp, vp],
+        "bfsearch_correlate_dense_range": [vp, vp, u32, u32, u32, u32, vp, vp, vp],
         "bfsearch_plan_spectra": [vp, u32, u32, u32, vp, vp],
         "bfsearch_job_spectra": [vp, vp],
     }
@@ -219,6 +221,12 @@ class Plan:
                 "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)],
                 "tile": ki.tile, "tile_us": {t: float(ki.tile_us[i]) for i, t in enumerate((1, 2, 4, 8, 16))}}
 
+    def held_bytes(self) -> int:
+        """Device bytes the plan holds now (plan memory, live jobs, pooled buffer sets)."""
+        info = PlanInfo()
+        _check(_lib.bfsearch_plan_get_info(self._h, ctypes.byref(info)), "bfsearch_plan_get_info")
+        return int(info.held_bytes)
+
     def job_bytes(self, lengths) -> int:
         """Device bytes a filter call over segments of these lengths holds while live."""
         lens = np.ascontiguousarray(np.asarray(lengths, dtype=np.uint32))
@@ -281,20 +289,22 @@ class Plan:
                                     _stream_handle(stream), ctypes.byref(h)), "bfsearch_filter")
         return Job(self, h, y, lens)
 
-    def correlate_dense(self, y, stream=None):
-        """Diagnostic: every rho value [S, K, n_s] (plan sample dtype) and sigma [S, K] (float64)
-        for segments y [S, n_s] of one accepted length n_s."""
+    def correlate_dense(self, y, first: int = 0, count: int | None = None, stream=None):
+        """Diagnostic: every rho value [S, count, n_s] (plan sample dtype) and sigma [S, count]
+        (float64) for segments y [S, n_s] of one accepted length n_s, against the templates
+        first..first+count-1 (default: the whole bank)."""
         import torch
 
         y = self._check_tensor(y)
         if y.dim() == 1:
             y = y.unsqueeze(0)
         s, n = y.shape
-        rho = torch.empty((s, self.k, n), dtype=y.dtype, device=y.device)
-        sig = torch.empty((s, self.k), dtype=torch.float64, device=y.device)
-        _check(_lib.bfsearch_correlate_dense(self._h, ctypes.c_void_p(y.data_ptr()), n, s,
-                                             ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
-                                             _stream_handle(stream)), "bfsearch_correlate_dense")
+        count = self.k - first if count is None else int(count)
+        rho = torch.empty((s, count, n), dtype=y.dtype, device=y.device)
+        sig = torch.empty((s, count), dtype=torch.float64, device=y.device)
+        _check(_lib.bfsearch_correlate_dense_range(self._h, ctypes.c_void_p(y.data_ptr()), n, s, int(first), count,
+                                                   ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sig.data_ptr()),
+                                                   _stream_handle(stream)), "bfsearch_correlate_dense_range")
         return rho, sig
 
     def spectra(self, first: int = 0, count: int | None = None, n: int | None = None, stream=None):

@@ -553,9 +553,12 @@ __device__ __forceinline__ bool tile_map(uint32_t b, uint32_t K, uint32_t S, uin
 }
 
 // One workgroup per (template j, spectrum row), in the order of tile_map over
-// a 1-D grid of 8 ceil(K/8) n_rows workgroups.
-//   bank  [K][M] packed template spectra (storage TW), yspec [n_rows][M] packed;
-//   row r is segment seg_ids[r] (or r), the id used for sigma and tails;
+// a 1-D grid of 8 ceil(K/8) n_rows workgroups.  A launch may cover a slice of
+// the bank and of the rows (the host splits grids that would be too large):
+//   bank  [K][M] packed template spectra (storage TW) of templates j0..j0+K-1,
+//   yspec [n_rows][M] packed; row r is segment seg_ids[r] (or row0 + r), the
+//   id used for sigma and tails; template ids are j0 + j, and sigma_out and
+//   rho_dense are indexed by segment * k_total + template id;
 //   proj (may be null): projection keys, row r's N lags at proj + proj_off[r].
 //   tw_u  exp(+2 pi i k / N), tw1/tw2 the FFT twiddles (see bfs_fft3.h).
 // z = IDFT_M(Z) gives z_n = N (rho_{2n} + i rho_{2n+1}); with
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
-    T* __restrict__ rho_dense) {
+    T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int M = F::M;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -576,7 +579,8 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
-  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row);
+  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row0 + row);
+  const uint32_t jg = j0 + j;  // template id in the whole bank
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   cx<T> v[F::P];
@@ -589,10 +593,10 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   corr_pre<F, MAP_MIRROR, G, T, TW, (F::P >= 32)>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
   const double S = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
   const double rootS = sqrt(S);
-  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
+  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
   auto z = [&](int i) { return v[i]; };
   if constexpr (DENSE) {
-    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * K + j) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
+    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * k_total + jg) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
     emit_dense<F, T>(z, 0u, N, rr, t);
   } else {
     const T thr = T(kappa * rootS);
@@ -603,7 +607,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
       unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
-      emit_tails<F, T>(z, 0u, thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z, 0u, thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
     }
   }
 }
@@ -622,7 +626,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
     tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
-    T* __restrict__ rho_dense) {
+    T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int H = F::M, M = 2 * H;
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
@@ -630,7 +634,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
-  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row);
+  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row0 + row);
+  const uint32_t jg = j0 + j;  // template id in the whole bank
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
   const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   cx<T> v[F::P];
@@ -667,7 +672,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   lds_barrier();  // every wave is done with the even half's LDS before the odd half writes it
   const double S = S0 + corr_ifft<F>(v, lds, red, cols, tw1, tw2, to, acc);
   const double rootS = sqrt(S);
-  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * K + j] = rootS / N;
+  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
 
   // v <- exp(2 pi i n / M) O_n
 #pragma unroll
@@ -681,7 +686,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
   auto z_lo = [&](int i) { return cadd(e[i], v[i]); };
   auto z_hi = [&](int i) { return csub(e[i], v[i]); };
   if constexpr (DENSE) {
-    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * K + j) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
+    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * k_total + jg) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
     emit_dense<F, T>(z_lo, 0u, N, rr, t);
     emit_dense<F, T>(z_hi, uint32_t(H), N, rr, t);
   } else {
@@ -696,8 +701,8 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const bool any = (mx > thr) && (rootS > 0.0);
     if (__ballot(any)) {
       unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
-      emit_tails<F, T>(z_lo, 0u, thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
-      emit_tails<F, T>(z_hi, uint32_t(H), thr, thr_hi, any, s, j, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z_lo, 0u, thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
+      emit_tails<F, T>(z_hi, uint32_t(H), thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
     }
   }
 }

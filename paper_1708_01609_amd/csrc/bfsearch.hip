@@ -123,31 +123,55 @@ struct Impl {
     return hipGetLastError();
   }
   template <bool DENSE>
-  static void launch_corr(dim3 grid, uint32_t S, uint32_t tile, hipStream_t st, const CorrArgs& a) {
-    const auto* bank = static_cast<const TW*>(a.bank);
-    const auto* y = static_cast<const cx<T>*>(a.y);
+  static void launch_corr(uint32_t blocks, const TW* bank, const cx<T>* y, const uint32_t* seg_ids,
+                          const uint64_t* proj_off, uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0,
+                          uint32_t row0, hipStream_t st, const CorrArgs& a) {
     const auto* tu = static_cast<const cx<T>*>(a.tw_u);
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
     if constexpr (SPLIT)
-      hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, a.kappa_hi, rho);
+      hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
+                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         a.kappa_hi, rho, j0, a.K, row0);
     else
-      hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), grid, dim3(F::NT), 0, st, bank, y, a.seg_ids, tu, t1, t2,
-                         a.K, S, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, a.proj_off, a.kappa_hi, rho);
+      hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
+                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         a.kappa_hi, rho, j0, a.K, row0);
   }
-  // 1-D grid in the XCD-aware order of tile_map: 8 ceil(K/8) S workgroups
+  // 1-D grids in the XCD-aware order of tile_map, 8 ceil(K/8) S workgroups in all.  A
+  // launch holds at most MAX_ITEMS work items (the dispatch's grid size is a 32-bit count
+  // of work items): larger jobs run as several launches over slices of the segment rows
+  // (each with every template), and of the bank too when one row alone is too large.
+  static constexpr uint64_t MAX_ITEMS = 1ull << 31;
   static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    const uint64_t blocks = 8ull * ((uint64_t(a.K) + 7) / 8) * S;
-    if (!S || blocks > 0x7fffffffull) return hipErrorInvalidValue;
-    const uint32_t tile = std::min<uint32_t>(std::max<uint32_t>(a.tile, 1u), S);
-    const dim3 grid(static_cast<uint32_t>(blocks));
-    if (dense)
-      launch_corr<true>(grid, S, tile, st, a);
-    else
-      launch_corr<false>(grid, S, tile, st, a);
-    return hipGetLastError();
+    if (!S || !a.K) return hipErrorInvalidValue;
+    const uint64_t max_blocks = MAX_ITEMS / F::NT;
+    uint64_t kc = a.K;  // templates per launch: all, or a multiple of 8 that fits one row
+    if (8ull * ((kc + 7) / 8) > max_blocks) kc = (max_blocks / 8) * 8;
+    const auto* bank = static_cast<const TW*>(a.bank);
+    const auto* y = static_cast<const cx<T>*>(a.y);
+    for (uint64_t j0 = 0; j0 < a.K; j0 += kc) {
+      const uint32_t kn = uint32_t(std::min<uint64_t>(kc, a.K - j0));
+      const uint64_t per_row = 8ull * ((kn + 7) / 8);
+      const uint32_t rows = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(S, max_blocks / per_row)));
+      for (uint32_t r0 = 0; r0 < S; r0 += rows) {
+        const uint32_t rn = std::min(rows, S - r0);
+        const uint32_t tile = std::min<uint32_t>(std::max<uint32_t>(a.tile, 1u), rn);
+        const uint32_t blocks = uint32_t(per_row * rn);
+        const TW* bk = bank + j0 * uint64_t(M);
+        const cx<T>* yr = y + uint64_t(r0) * M;
+        const uint32_t* ids = a.seg_ids ? a.seg_ids + r0 : nullptr;
+        const uint64_t* po = a.proj_off ? a.proj_off + r0 : nullptr;
+        if (dense)
+          launch_corr<true>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+        else
+          launch_corr<false>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
+    }
+    return hipSuccess;
   }
   static hipError_t export_bank(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first) {
     const dim3 grid((M + 1 + 255) / 256, count);
@@ -399,7 +423,8 @@ struct bfs_plan {
   std::vector<std::pair<hipStream_t, hipStream_t>> corr_streams;  // caller stream -> paired stream
   std::vector<hipStream_t> owned_streams;
   std::mutex mu;
-  std::vector<JobBuffers*> pool;
+  std::vector<JobBuffers*> pool;  // released buffer sets (still allocated on the device)
+  uint64_t pool_bytes = 0;         // their device bytes
   uint64_t live_job_bytes = 0;
   int live_jobs = 0;
 };
@@ -735,6 +760,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
     if (covers(p->pool[i]->cap, need)) {
       *out = p->pool[i];
       p->pool.erase(p->pool.begin() + long(i));
+      p->pool_bytes -= (*out)->bytes;
       p->live_job_bytes += (*out)->bytes;
       ++p->live_jobs;
       return BFS_OK;
@@ -755,6 +781,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   }
   for (auto* b : p->pool) free_job_buffers(b);
   p->pool.clear();
+  p->pool_bytes = 0;
   if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) return BFS_ERR_OUT_OF_MEMORY;
   auto* b = new (std::nothrow) JobBuffers();
   if (!b) return BFS_ERR_OUT_OF_MEMORY;
@@ -792,6 +819,7 @@ void put_job_buffers(bfs_plan* p, JobBuffers* b) {
   p->live_job_bytes -= b->bytes;
   --p->live_jobs;
   p->pool.push_back(b);
+  p->pool_bytes += b->bytes;
 }
 
 const SizePlan* size_plan(const bfs_plan* p, uint32_t n) {
@@ -902,7 +930,8 @@ bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
 // (projection plans) the compaction of the projection keys.  ev[1] / ev[2]
 // bracket the correlation kernels when with_events is set.
 bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
-                        hipStream_t cs, bool with_events) {
+                        hipStream_t cs, bool with_events, uint32_t first = 0, uint32_t count = 0) {
+  if (!count) count = p->K;
   const uint32_t S = uint32_t(L.seg_len.size());
   const bool project = p->project && !dense;
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
@@ -912,13 +941,13 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   if (with_events) HIP_TRY(hipEventRecord(b->ev[1], cs));
   for (const Group& g : L.groups) {
     CorrArgs c{};
-    c.bank = g.sp->bank;
+    c.bank = static_cast<const char*>(g.sp->bank) + uint64_t(first) * g.sp->M * g.sp->ks->spec_size;
     c.y = ybase + g.y_off;
     c.seg_ids = dids + g.first;
     c.tw_u = g.sp->tw_u;
     c.tw1 = g.sp->tw1;
     c.tw2 = g.sp->tw2;
-    c.K = p->K;
+    c.K = count;
     c.tile = g.sp->tile;
     c.kappa = p->kappa;
     c.kappa_hi = p->kappa_hi;
@@ -944,10 +973,10 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
 
 // The whole job on one stream (graph capture, dense correlation).
 bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
-                        hipStream_t st, bool with_events) {
+                        hipStream_t st, bool with_events, uint32_t first = 0, uint32_t count = 0) {
   const bfs_status rs = enqueue_prep(p, b, L, dense, st);
   if (rs != BFS_OK) return rs;
-  return enqueue_corr(p, b, L, dense, rho, sigma, st, with_events);
+  return enqueue_corr(p, b, L, dense, rho, sigma, st, with_events, first, count);
 }
 
 // The correlation stream paired with the caller's stream st (created on first
@@ -1022,14 +1051,14 @@ bfs_status launch_graph(bfs_plan* p, JobBuffers* b, const Layout& L, hipStream_t
 // done.  Graph plans and dense correlations keep the whole job on st.
 // *done_stream is the stream that event was recorded on.
 bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
-                     hipStream_t st, hipStream_t* done_stream) {
+                     hipStream_t st, hipStream_t* done_stream, uint32_t first = 0, uint32_t count = 0) {
   *done_stream = st;
   HIP_TRY(hipEventRecord(b->ev[0], st));
   if (p->graph && !dense) {
     const bfs_status rs = launch_graph(p, b, L, st);
     if (rs != BFS_OK) return rs;
   } else if (dense) {
-    const bfs_status rs = enqueue_body(p, b, L, dense, rho, sigma, st, true);
+    const bfs_status rs = enqueue_body(p, b, L, dense, rho, sigma, st, true, first, count);
     if (rs != BFS_OK) return rs;
   } else {
     hipStream_t cs = nullptr;
@@ -1073,7 +1102,14 @@ bool ensure_sort(bfs_plan* p, JobBuffers* b, uint64_t n) {
   if (!work) return false;
   const uint64_t bytes = sort_out_bytes(want) + work;
   std::lock_guard<std::mutex> lk(p->mu);
-  if (p->plan_bytes + p->live_job_bytes - b->sort_bytes + bytes > p->budget) return false;
+  // the pooled buffer sets still hold device memory: count them, and give them back to the
+  // device when the sort area fits only without them
+  if (p->plan_bytes + p->live_job_bytes + p->pool_bytes - b->sort_bytes + bytes > p->budget) {
+    if (p->plan_bytes + p->live_job_bytes - b->sort_bytes + bytes > p->budget) return false;
+    for (auto* q : p->pool) free_job_buffers(q);
+    p->pool.clear();
+    p->pool_bytes = 0;
+  }
   if (b->sorted) (void)hipFree(b->sorted);
   p->live_job_bytes -= b->sort_bytes;
   b->bytes -= b->sort_bytes;
@@ -1237,6 +1273,10 @@ bfs_status bfsearch_plan_get_info(const bfs_plan* p, bfs_plan_info* out) {
   out->plan_bytes = p->plan_bytes;
   out->precision = uint32_t(p->prec);
   out->n_min = p->n_min;
+  {
+    std::lock_guard<std::mutex> lk(const_cast<bfs_plan*>(p)->mu);
+    out->held_bytes = p->plan_bytes + p->live_job_bytes + p->pool_bytes;
+  }
   return BFS_OK;
 }
 
@@ -1463,15 +1503,18 @@ bfs_status bfsearch_destroy(bfs_plan* p) {
   return BFS_OK;
 }
 
-bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg_len, uint32_t S, void* rho_dev,
-                                    double* sigma_dev, void* hip_stream) {
+bfs_status bfsearch_correlate_dense_range(bfs_plan* p, const void* y_dev, uint32_t seg_len, uint32_t S,
+                                          uint32_t first, uint32_t count, void* rho_dev, double* sigma_dev,
+                                          void* hip_stream) {
   if (!p || !y_dev || !rho_dev || S < 1 || S > 65535) return BFS_ERR_INVALID_ARG;
+  if (count < 1 || uint64_t(first) + count > p->K) return BFS_ERR_INVALID_ARG;
   if (!seg_len) seg_len = p->n_max;
   if (!size_plan(p, seg_len)) return BFS_ERR_INVALID_ARG;
   std::vector<uint32_t> lens(S, seg_len);
   Layout L;
   bfs_status rs = make_layout(p, lens.data(), S, L);
   if (rs != BFS_OK) return rs;
+  L.need.sigma = uint64_t(S) * count;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   JobBuffers* b = nullptr;
@@ -1479,11 +1522,17 @@ bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg
   if (rs != BFS_OK) return rs;
   stage_table(p, y_dev, nullptr, L, b->meta_host);
   hipStream_t done_st = st;
-  rs = queue_job(p, b, L, true, rho_dev, sigma_dev, st, &done_st);
+  rs = queue_job(p, b, L, true, rho_dev, sigma_dev, st, &done_st, first, count);
   // the buffers go back to the pool only after the queued kernels finish
   (void)hipStreamSynchronize(st);
   put_job_buffers(p, b);
   return rs;
+}
+
+bfs_status bfsearch_correlate_dense(bfs_plan* p, const void* y_dev, uint32_t seg_len, uint32_t S, void* rho_dev,
+                                    double* sigma_dev, void* hip_stream) {
+  if (!p) return BFS_ERR_INVALID_ARG;
+  return bfsearch_correlate_dense_range(p, y_dev, seg_len, S, 0, p->K, rho_dev, sigma_dev, hip_stream);
 }
 
 bfs_status bfsearch_plan_spectra(const bfs_plan* p, uint32_t n, uint32_t first, uint32_t count, double* out_dev,

@@ -13,12 +13,18 @@ The scheduler is host logic only and talks to an executor:
     job_bytes(lengths) -> int            device bytes of a job of these lengths
     submit(slot, requests) -> handle     queue a job on the slot's stream
     ready(handle) -> bool                non-blocking completion check
-    collect(handle) -> [(tails, sigma)]  per request: its tails (segment field
-                                         = position in the job) and sigma [K]
+    collect(handle) -> [(tails, sigma, complete)]
+                                         per request: its tails (segment field
+                                         = position in the job), sigma [K] and
+                                         whether the tail list is complete
 GpuExecutor runs jobs through the library; tests drive the scheduler with a
 CPU stand-in.  Each correlation is computed by one workgroup with a fixed
 reduction order, so a request's result does not depend on which requests
-share its job.
+share its job.  A job whose tails overflowed the device buffer returns its
+requests flagged incomplete (the device counts every tail but keeps only as
+many as fit, in no particular order), and they are counted as truncated.  An
+executor error in submit or collect fails that job's requests only; the slot
+is freed and serving goes on.
 """
 from __future__ import annotations
 
@@ -47,6 +53,7 @@ class Result:
     done_wall: float
     job: int                # sequence number of the job it ran in
     batch: int              # requests in that job
+    complete: bool = True   # False: the job's tails overflowed, this list may miss some
 
     @property
     def latency(self) -> float:
@@ -61,6 +68,7 @@ class Result:
 class ServeStats:
     results: dict = field(default_factory=dict)
     rejected: list = field(default_factory=list)
+    failed: list = field(default_factory=list)    # (rid, error text) of requests whose job raised
     wall_s: float = 0.0
     jobs: int = 0
     max_inflight: int = 0
@@ -75,6 +83,8 @@ class ServeStats:
         return {
             "requests": n,
             "rejected": len(self.rejected),
+            "failed": len(self.failed),
+            "truncated": sum(1 for r in self.results.values() if not r.complete),
             "jobs": self.jobs,
             "mean_batch": n / max(self.jobs, 1),
             "max_inflight_jobs": self.max_inflight,
@@ -118,7 +128,7 @@ def serve(executor, requests, slots: int = 4, max_batch: int = 16, budget_bytes:
     while pending or waiting or inflight:
         now = clock()
         if progress is not None and now >= next_report:
-            progress(len(stats.results) + len(stats.rejected), n_total, now - t0)
+            progress(len(stats.results) + len(stats.rejected) + len(stats.failed), n_total, now - t0)
             next_report = now + progress_every_s
         while pending and arrival_wall(pending[0]) <= now:
             waiting.append(pending.popleft())
@@ -126,15 +136,22 @@ def serve(executor, requests, slots: int = 4, max_batch: int = 16, budget_bytes:
         # completions
         for slot in list(inflight):
             handle, reqs, nbytes, t_adm, jid = inflight[slot]
-            if not executor.ready(handle):
-                continue
-            per_req = executor.collect(handle)
+            try:
+                if not executor.ready(handle):
+                    continue
+                per_req = executor.collect(handle)
+            except Exception as e:  # the job failed: its requests only
+                stats.failed.extend((r.rid, repr(e)) for r in reqs)
+                per_req = None
             t_done = clock()
-            for pos, (r, (tails, sigma)) in enumerate(zip(reqs, per_req)):
+            for r, res in zip(reqs, per_req or ()):
+                tails, sigma = res[0], res[1]
+                complete = bool(res[2]) if len(res) > 2 else True
                 t = tails.copy()
                 if len(t):
                     t["segment"] = r.rid
-                stats.results[r.rid] = Result(r.rid, t, sigma, arrival_wall(r), t_adm, t_done, jid, len(reqs))
+                stats.results[r.rid] = Result(r.rid, t, sigma, arrival_wall(r), t_adm, t_done, jid, len(reqs),
+                                              complete)
             inflight_bytes -= nbytes
             del inflight[slot]
             free.append(slot)
@@ -156,7 +173,13 @@ def serve(executor, requests, slots: int = 4, max_batch: int = 16, budget_bytes:
                 break
             slot = free.pop()
             t_adm = clock()
-            handle = executor.submit(slot, batch)
+            try:
+                handle = executor.submit(slot, batch)
+            except Exception as e:  # nothing was queued: fail these requests, keep the slot
+                stats.failed.extend((r.rid, repr(e)) for r in batch)
+                free.append(slot)
+                progressed = True
+                continue
             inflight[slot] = (handle, batch, nbytes, t_adm, stats.jobs)
             stats.jobs += 1
             inflight_bytes += nbytes
@@ -209,11 +232,12 @@ class GpuExecutor:
         return job.done()
 
     def collect(self, job):
-        tails, total = job.fetch_tails(allow_overflow=True)
-        sigma = job.fetch_sigma()
-        job.release()
-        out = []
+        try:
+            tails, total = job.fetch_tails(allow_overflow=True)
+            sigma = job.fetch_sigma()
+        finally:
+            job.release()
+        # on overflow the device kept an arbitrary subset: no request's list is known complete
+        complete = total == len(tails)
         seg = tails["segment"]
-        for s in range(job.n_segments):
-            out.append((tails[seg == s], sigma[s]))
-        return out
+        return [(tails[seg == s], sigma[s], complete) for s in range(job.n_segments)]

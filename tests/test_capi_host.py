@@ -45,7 +45,7 @@ def test_library_exports_every_declared_symbol(bfs):
 
 
 def test_struct_layouts_match_header(bfs):
-    assert ctypes.sizeof(bfs.PlanInfo) == 40
+    assert ctypes.sizeof(bfs.PlanInfo) == 48
     assert bfs.TAIL_DTYPE.itemsize == 24
     assert bfs.PEAK_DTYPE.itemsize == 16
     # bfs_plan_desc field order as declared (spot-check offsets of the 64-bit fields)
@@ -139,6 +139,7 @@ def test_null_handles_are_rejected(bfs):
     assert lib.bfsearch_job_release(None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_destroy(None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_correlate_dense(None, None, 0, 1, None, None, None) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_correlate_dense_range(None, None, 0, 1, 0, 1, None, None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_plan_spectra(None, 0, 0, 1, None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_job_spectra(None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_job_timing(None, None, None) == bfs.BFS_ERR_INVALID_ARG

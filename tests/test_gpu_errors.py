@@ -98,3 +98,56 @@ def test_fp64_uneven_lengths_match_oracle(bfs):
     common, band = compare_tails(tails, out["tails"], out["sigma"], kappa, TOL["f64"],
                                  lambda s, j: out["rho"][s][j])
     assert common > 100 and band <= 2
+
+
+def test_grid_of_2_to_32_work_items_matches_smaller_calls(bfs):
+    # 8192 chirps x 512 segments of 2^16 samples = 8 * 1024 * 512 workgroups of 1024 threads,
+    # 2^32 work items: more than one dispatch's 32-bit grid holds.  The library splits the
+    # launch; the result equals eight calls of 64 segments, bitwise
+    n, S = 1 << 16, 512
+    ys = np.random.default_rng(34).standard_normal((S, n), dtype=np.float32)
+    grid = bfs.Grid(128, 64, (350.0, 2000.0), (-500.0, 500.0), (1.0,))
+    with bfs.Plan(n, 4096.0, kappa=5.5, grid=grid, precision="f32", tail_capacity=1 << 20) as plan:
+        assert 8 * (plan.k // 8) * S * plan.threads_per_correlation == 1 << 32
+        with plan.filter(_dev(ys)) as job:
+            tails, total = job.fetch_tails()
+            sig = job.fetch_sigma()
+        parts_t, parts_s = [], []
+        for s0 in range(0, S, 64):
+            with plan.filter(_dev(ys[s0:s0 + 64])) as job:
+                t, _ = job.fetch_tails()
+                t["segment"] += s0
+                parts_t.append(t)
+                parts_s.append(job.fetch_sigma())
+    assert total == len(tails) > 0
+    assert np.array_equal(np.concatenate(parts_t), tails)
+    assert np.array_equal(np.concatenate(parts_s), sig)
+
+
+def test_device_sort_area_counts_pooled_buffers(bfs):
+    # a released job's buffers stay allocated for reuse; the device sort area of a large
+    # fetch must fit the budget with them counted, or they are given back first
+    n, S, K = 4096, 3, 5
+    rng = np.random.default_rng(35)
+    ys = _dev(rng.standard_normal((S, n)).astype(np.float32))
+    kw = dict(kappa=0.0, templates=rng.standard_normal((K, 300)), precision="f32", tail_capacity=S * K * n)
+
+    def run(budget):
+        with bfs.Plan(n, 4096.0, hbm_budget_bytes=budget, **kw) as plan:
+            plan_b, job_b = plan.held_bytes(), plan.job_bytes([n] * S)
+            j1 = plan.filter(ys)
+            j2 = plan.filter(ys)
+            j2.release()  # its buffer set goes to the pool
+            tails, total = j1.fetch_tails()  # 61,440 tails: ordered on the device
+            held = plan.held_bytes()
+            j1.release()
+        return tails, total, plan_b, job_b, held
+
+    t0, tot0, plan_b, job_b, held0 = run(0)
+    sort_b = held0 - plan_b - 2 * job_b
+    assert tot0 == S * K * n and sort_b > job_b // 2
+    budget = plan_b + job_b + sort_b + job_b // 2
+    t1, tot1, _, _, held1 = run(budget)
+    assert held1 <= budget
+    assert held1 == plan_b + job_b + sort_b  # the pooled set was freed to make room
+    assert tot1 == tot0 and np.array_equal(t0, t1)

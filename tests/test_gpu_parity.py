@@ -11,7 +11,8 @@ import pytest
 
 import oracle
 from synthetic import get_workload, make_segment
-from tests.parity import TOL, compare_tails, max_rel_err, sigma_floor
+from tests.parity import (BF16_MODEL_BOUND, TOL, compare_tails, max_rel_err, relaxed_mask, row_abs_err,
+                          sigma_floor, strict_report, tol_scale)
 
 pytestmark = pytest.mark.gpu
 
@@ -172,57 +173,77 @@ def c2_oracle():
     return w, y, bank, oracle.search([y], bank, w.kappa)
 
 
-def test_c2_fp32_tails_sigma_and_sampled_rho(bfs, c2_oracle):
-    # C2 at full size in the launch configuration the bench times: N = 2^16, 8192 chirps, kappa = 5
+def _dense_blocks(plan, y_dev, y64, temps, first=0, block=1024):
+    """Per template of temps (ids first.. of the plan): max |rho_gpu - rho_oracle| over every
+    lag, sigma_gpu and the oracle's sigma, taken block by block through the dense diagnostic."""
+    k = len(temps)
+    err, sg, so = np.empty(k), np.empty(k), np.empty(k)
+    for j0 in range(0, k, block):
+        c = min(block, k - j0)
+        rho_g, sig_g = plan.correlate_dense(y_dev, first=first + j0, count=c)
+        rho_g, sig_g = rho_g.cpu().numpy()[0], sig_g.cpu().numpy()[0]
+        rho_o = oracle.correlate_fft(y64, np.array(temps[j0:j0 + c]))
+        err[j0:j0 + c] = row_abs_err(rho_g, rho_o)
+        sg[j0:j0 + c] = sig_g
+        so[j0:j0 + c] = oracle.sigma_time(rho_o)
+        del rho_g, rho_o
+    return err, sg, so
+
+
+def test_c2_fp32_tails_sigma_and_dense_rho(bfs, c2_oracle):
+    # C2 at full size in the launch configuration the bench times: N = 2^16, 8192 chirps,
+    # kappa = 5.  Every rho of every template against the oracle: strict 1e-4 sigma wherever
+    # sigma >= 0.1 sigma_floor, 1e-4 * 0.1 sigma_floor below (templates almost wholly outside
+    # the data band, 138 of 8192 here)
     w, y, bank, out = c2_oracle
     w2, y2, inj, plan, tails, total, sig = _workload_run(bfs, "C2")
     assert np.array_equal(y, y2)
     assert total == len(tails) and total > 100
-    assert np.max(np.abs(sig - out["sigma"]) / out["sigma"]) <= TOL["f32"]
 
     def rho_row(s, j):
         return oracle.correlate_fft(y.astype(np.float64), bank[j])
 
     floor = np.array([[sigma_floor(bank[j], y) for j in range(w.n_templates)]])
+    assert np.max(np.abs(sig - out["sigma"]) / tol_scale(out["sigma"], floor)) <= TOL["f32"]
     common, band = compare_tails(tails, out["tails"], out["sigma"], w.kappa, TOL["f32"], rho_row, floor)
     assert common >= 0.99 * len(out["tails"])
-    # sampled dense rows: every lag of 12 templates spread over the bank (the first lies almost
-    # wholly below the band: sigma ~ 2e-4 of in-band, so the input-scale floor applies)
-    pick = np.linspace(0, w.n_templates - 1, 12).astype(int)
-    rho_g, _ = plan.correlate_dense(_dev(y, np.float32))
-    rho_g = rho_g.cpu().numpy()[0]
-    worst = 0.0
-    for j in pick:
-        ro = rho_row(0, j)
-        scale = max(out["sigma"][0, j], floor[0, j])
-        e = np.max(np.abs(rho_g[j] - ro)) / scale
-        worst = max(worst, e)
-        assert e <= TOL["f32"], (j, e)
-    print(f"C2 sampled rho: max err / max(sigma, floor) = {worst:.3e}; common tails {common}, band-only {band}")
+    err, sg, so = _dense_blocks(plan, _dev(y, np.float32), y.astype(np.float64), bank)
+    rep = strict_report(err, so, floor[0])
+    print(f"C2 dense rho, {w.n_templates} templates: {rep}; sigma max rel err (strict set) "
+          f"{np.max(np.abs(sg - so)[~relaxed_mask(so, floor[0])] / so[~relaxed_mask(so, floor[0])]):.3e}; "
+          f"common tails {common}, band-only {band}")
+    assert rep["n_relaxed"] <= 200
+    assert rep["strict_max_err_over_sigma"] <= TOL["f32"]
+    assert np.all(err <= TOL["f32"] * tol_scale(so, floor[0]))
+    assert np.all(np.abs(sg - so) <= TOL["f32"] * tol_scale(so, floor[0]))
     plan.close()
 
 
-@pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"])
+@pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"], ids=["fp16-meets-2e-3", "bf16-misses-2e-3-within-error-model"])
 def test_reduced_precision_spectra_error(bfs, prec):
-    # precision form: template spectra stored 16-bit, FFT and accumulation FP32, sigma FP64.
-    # FP16 must meet 2e-3 sigma; BF16 is expected to miss it (8-bit mantissa) and is held to 2e-2.
+    # precision form: template spectra stored 16-bit, FFT and accumulation FP32, sigma FP64; every
+    # rho of all 8192 C2 templates against the oracle.  FP16 meets the 2e-3 sigma bar.  BF16's
+    # 8-bit mantissa misses it (predicted ~1e-2 sigma worst case): held to the error model's bound
+    # and reported, not passed under a widened bar.
     w = get_workload("C2")
     y, _ = make_segment(w, 0)
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
     f0, fd, tau = w.template_params()
-    pick = np.linspace(0, w.n_templates - 1, 8).astype(int)
+    temps = oracle.template_bank(f0, fd, tau, w.fs)
+    floor = np.array([sigma_floor(t, y) for t in temps])
     with bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=prec) as plan:
-        rho_g, sig_g = plan.correlate_dense(_dev(y, np.float32))
-        rho_g = rho_g.cpu().numpy()[0][pick]
-        sig_g = sig_g.cpu().numpy()[0][pick]
-    temps = oracle.template_bank(f0, fd, tau, w.fs, ids=pick)
-    rho_o = oracle.correlate_fft(y.astype(np.float64), np.array(temps))
-    sig_o = oracle.sigma_time(rho_o)
-    scale = np.maximum(sig_o, [sigma_floor(t, y) for t in temps])
-    err = max_rel_err(rho_g, rho_o, scale)
-    print(f"{prec}: max |rho err| / sigma = {err:.3e}")
-    assert err <= TOL[prec]
-    assert np.max(np.abs(sig_g - sig_o) / scale) <= TOL[prec]
+        err, sg, so = _dense_blocks(plan, _dev(y, np.float32), y.astype(np.float64), temps)
+    rep = strict_report(err, so, floor)
+    sig_err = float(np.max(np.abs(sg - so) / tol_scale(so, floor)))
+    meets = rep["strict_max_err_over_sigma"] <= TOL[prec] and np.all(err <= TOL[prec] * tol_scale(so, floor))
+    print(f"{prec}: dense rho over 8192 templates {rep}; sigma err/scale {sig_err:.3e}; "
+          f"meets 2e-3 sigma: {bool(meets)}")
+    assert sig_err <= TOL[prec]
+    if prec == "f32-w16f":
+        assert meets
+    else:
+        assert rep["strict_max_err_over_sigma"] <= BF16_MODEL_BOUND
+        assert np.all(err <= BF16_MODEL_BOUND * tol_scale(so, floor))
 
 
 def test_kappa_zero_returns_every_lag(bfs):
@@ -343,7 +364,7 @@ def test_uneven_segments_in_one_call_match_oracle_and_single_calls(bfs):
     assert np.array_equal(np.stack(alone_s), sig)
     out = oracle.search([y.astype(np.float64) for y in segs], temps, w.kappa)
     floor = np.array([[sigma_floor(t, y) for t in temps] for y in segs])
-    assert np.max(np.abs(sig - out["sigma"]) / np.maximum(out["sigma"], floor)) <= TOL["f32"]
+    assert np.max(np.abs(sig - out["sigma"]) / tol_scale(out["sigma"], floor)) <= TOL["f32"]
     common, band = compare_tails(tails, out["tails"], out["sigma"], w.kappa, TOL["f32"],
                                  lambda s, j: oracle.correlate_fft(segs[s].astype(np.float64), temps[j]), floor)
     print(f"uneven: {total} tails, common {common}, band-only {band}, lengths {lens}")
@@ -429,10 +450,11 @@ def test_autotuned_plan_reports_timings_and_stays_correct(bfs):
             assert info["tile_us"][info["tile"]] == min(info["tile_us"].values())
 
 
-@pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"])
+@pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"], ids=["fp16", "bf16"])
 def test_c3_full_dense_bank_16bit_against_oracle_subset(bfs, prec):
     # C3: the C2 segment against all 1,048,576 chirps with 16-bit spectra resident (128 GiB);
-    # sigma and tails of templates 0..4095 against the FP64 oracle at the 16-bit tolerance
+    # templates 0..4095 against the FP64 oracle: every rho (dense), sigma and the tails.  FP16 is
+    # held to 2e-3 sigma; BF16 to its error model's bound (it misses 2e-3, reported)
     w = get_workload("C3")
     y, _ = make_segment(w, 0)
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus)
@@ -440,16 +462,23 @@ def test_c3_full_dense_bank_16bit_against_oracle_subset(bfs, prec):
     ids = np.arange(4096)
     temps = oracle.template_bank(f0, fd, tau, w.fs, ids=ids)
     out = oracle.search([y.astype(np.float64)], temps, w.kappa)
+    floor = np.array([[sigma_floor(t, y) for t in temps]])
+    bound = TOL[prec] if prec == "f32-w16f" else BF16_MODEL_BOUND
     with bfs.Plan(w.n, w.fs, kappa=w.kappa, grid=grid, precision=prec, tail_capacity=1 << 22) as plan:
         assert plan.k == 1 << 20 and plan.bank_bytes == (1 << 20) * (w.n // 2) * 4
-        with plan.filter(_dev(y, np.float32)) as job:
+        y_dev = _dev(y, np.float32)
+        with plan.filter(y_dev) as job:
             tails, total = job.fetch_tails()
             sig = job.fetch_sigma()[:, :4096]
+        err, sg, so = _dense_blocks(plan, y_dev, y.astype(np.float64), temps)
+    rep = strict_report(err, so, floor[0])
+    print(f"C3 {prec} dense rho, templates 0..4095: {rep}")
+    assert np.array_equal(sg, sig[0])
+    assert np.max(np.abs(sig - out["sigma"]) / tol_scale(out["sigma"], floor)) <= TOL[prec]
+    assert rep["strict_max_err_over_sigma"] <= bound
+    assert np.all(err <= bound * tol_scale(so, floor[0]))
     sub = tails[tails["template"] < 4096]
-    floor = np.array([[sigma_floor(t, y) for t in temps]])
-    scale = np.maximum(out["sigma"], floor)
-    assert np.max(np.abs(sig - out["sigma"]) / scale) <= TOL[prec]
-    common, band = compare_tails(sub, out["tails"], out["sigma"], w.kappa, TOL[prec],
+    common, band = compare_tails(sub, out["tails"], out["sigma"], w.kappa, bound,
                                  lambda s, j: oracle.correlate_fft(y.astype(np.float64), temps[j]), floor)
     print(f"C3 {prec}: {total} tails over 2^20 templates; subset common {common}, band-only {band}")
 
@@ -524,7 +553,7 @@ def test_band_threshold_matches_oracle(bfs):
     out = oracle.search([y.astype(np.float64)], temps, kappa, kappa_hi=kappa_hi)
     sig = out["sigma"][0]
     floor = np.array([sigma_floor(t, y) for t in temps])
-    tol = TOL["f32"] * np.maximum(sig, floor) / sig  # in units of sigma
+    tol = TOL["f32"] * tol_scale(sig, floor) / sig  # in units of sigma
     g = {(int(j), int(n)): float(r) for j, n, r in zip(tails["template"], tails["lag"], tails["rho"])}
     o = {(int(j), int(n)): float(r) for j, n, r in zip(out["tails"]["template"], out["tails"]["lag"], out["tails"]["rho"])}
     rows = {}
@@ -537,7 +566,7 @@ def test_band_threshold_matches_oracle(bfs):
 
     only = (g.keys() - o.keys()) | (o.keys() - g.keys())
     assert all(near_edge(j, n) for j, n in only)
-    assert all(abs(g[k] - o[k]) <= TOL["f32"] * max(sig[k[0]], floor[k[0]]) for k in g.keys() & o.keys())
+    assert all(abs(g[k] - o[k]) <= TOL["f32"] * tol_scale(sig[k[0]], floor[k[0]]) for k in g.keys() & o.keys())
     assert all(kappa < abs(r) / sig[j] < kappa_hi + tol[j] for (j, n), r in g.items())
     print(f"band: {total} GPU tails, {len(o)} oracle, {len(only)} differ within the band edges")
     assert len(g.keys() & o.keys()) > 1000 and len(only) <= len(o) // 100

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from synthetic import get_workload
-from tests.parity import TOL, compare_tails, sigma_floor
+from tests.parity import TOL, compare_tails, sigma_floor, tol_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -73,7 +73,7 @@ def test_served_mix_equals_alone_and_oracle(bfs, prec):
         t = got.tails.copy()
         t["segment"] = 0
         floor = np.array([[sigma_floor(tm, r.samples) for tm in temps]])
-        scale = np.maximum(out["sigma"][0], floor[0])
+        scale = tol_scale(out["sigma"][0], floor[0])
         assert np.max(np.abs(got.sigma - out["sigma"][0]) / scale) <= TOL[prec]
         compare_tails(t, out["tails"], out["sigma"], kappa, TOL[prec],
                       lambda s, j: oracle.correlate_fft(r.samples.astype(np.float64), temps[j]), floor)

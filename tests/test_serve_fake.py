@@ -51,7 +51,48 @@ class FakeExecutor:
         self.log.append(("done", self.clock.now(), h["slot"], None))
         out = h["out"]
         t = out["tails"]
-        return [(t[t["segment"] == s], out["sigma"][s]) for s in range(h["n"])]
+        return [(t[t["segment"] == s], out["sigma"][s], True) for s in range(h["n"])]
+
+
+class OverflowingExecutor(FakeExecutor):
+    """Keeps at most `cap` tails per job, like the device buffer, and says so."""
+
+    def __init__(self, *a, cap=5, **kw):
+        super().__init__(*a, **kw)
+        self.cap = cap
+
+    def collect(self, h):
+        per = super().collect(h)
+        total = sum(len(t) for t, _, _ in per)
+        if total <= self.cap:
+            return per
+        kept, out = 0, []
+        for t, sg, _ in per:
+            k = max(0, min(len(t), self.cap - kept))
+            kept += k
+            out.append((t[:k], sg, False))
+        return out
+
+
+class FailingExecutor(FakeExecutor):
+    """Raises in submit for jobs holding a request id in fail_submit, in collect for fail_collect."""
+
+    def __init__(self, *a, fail_submit=(), fail_collect=(), **kw):
+        super().__init__(*a, **kw)
+        self.fail_submit, self.fail_collect = set(fail_submit), set(fail_collect)
+
+    def submit(self, slot, reqs):
+        if self.fail_submit & {r.rid for r in reqs}:
+            raise RuntimeError("submit failed")
+        h = super().submit(slot, reqs)
+        h["rids"] = {r.rid for r in reqs}
+        return h
+
+    def collect(self, h):
+        if self.fail_collect & h["rids"]:
+            del self.busy[h["slot"]]
+            raise RuntimeError("collect failed")
+        return super().collect(h)
 
 
 def _requests(count, rate, seed, lengths=(256, 512, 1024)):
@@ -130,3 +171,44 @@ def test_replay_speed_scales_arrivals(bank):
 def test_invalid_parameters():
     with pytest.raises(ValueError):
         serve(None, [], slots=0)
+
+
+def test_overflowed_jobs_flag_their_requests_incomplete(bank):
+    # a job whose tails overflow returns partial lists: every request of that job is flagged,
+    # counted as truncated, and the complete ones keep their full result
+    clk = VirtualClock()
+    ex = OverflowingExecutor(bank, 1.0, clk, cap=40)
+    reqs = _requests(12, rate=100.0, seed=6)
+    st = serve(ex, reqs, slots=2, max_batch=3, clock=clk.now, sleep=clk.sleep)
+    assert sorted(st.results) == list(range(12))
+    flagged = {rid for rid, r in st.results.items() if not r.complete}
+    assert flagged and st.summary(len(bank))["truncated"] == len(flagged)
+    for rid, r in st.results.items():
+        alone = oracle.search([reqs[rid].samples], bank, 1.0)
+        if r.complete:
+            assert len(r.tails) == len(alone["tails"])
+        else:
+            assert len(r.tails) <= len(alone["tails"])
+    # jobs are flagged as a whole: requests sharing a job share the flag
+    by_job = {}
+    for r in st.results.values():
+        by_job.setdefault(r.job, set()).add(r.complete)
+    assert all(len(v) == 1 for v in by_job.values())
+
+
+def test_executor_errors_fail_only_their_job(bank):
+    # submit raising for request 3's job, collect raising for request 7's: those jobs' requests
+    # fail, their slots come back, and every other request is served with its own result
+    clk = VirtualClock()
+    ex = FailingExecutor(bank, 3.0, clk, fail_submit={3}, fail_collect={7})
+    reqs = _requests(16, rate=50.0, seed=7)
+    st = serve(ex, reqs, slots=2, max_batch=2, clock=clk.now, sleep=clk.sleep)
+    failed = {rid for rid, _ in st.failed}
+    assert 3 in failed and 7 in failed
+    assert failed.isdisjoint(st.results) and len(failed) + len(st.results) == 16
+    assert len(failed) <= 4 and not ex.busy
+    s = st.summary(len(bank))
+    assert s["failed"] == len(failed) and s["requests"] == len(st.results)
+    for rid, r in st.results.items():
+        alone = oracle.search([reqs[rid].samples], bank, 3.0)
+        assert np.array_equal(r.sigma, alone["sigma"][0])
