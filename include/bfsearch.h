@@ -76,6 +76,18 @@ typedef enum {
                                  shape, Fig. 2 caption), for ascending and
                                  descending chirps alike */
 
+#define BFS_PLAN_PAIRS 16u    /* detector pairs (Sec. 3.2 step (i), Sec. 5): the
+                                 segments of a filter call come as time-aligned
+                                 channel pairs, pair p's channels at segments 2p
+                                 and 2p + 1 (equal lengths).  Each (pair, template)
+                                 is correlated through one complex inverse
+                                 transform carrying both channels (real part:
+                                 channel 2p, imaginary part: channel 2p + 1);
+                                 tails, sigma and projections are reported per
+                                 segment as for single segments.  Lengths whose
+                                 transform the library splits (2^17 FP32, 2^14
+                                 FP64) are BFS_ERR_UNSUPPORTED */
+
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
 
@@ -99,6 +111,21 @@ typedef struct {
   uint32_t template_id;
   float snr;
 } bfs_peak;
+
+/* One coincidence of a detector pair (24 bytes): at lag `lag` both channels of
+ * pair `pair` carry a per-lag max-projected hit and the initial frequencies of
+ * the two winning templates differ by less than the plan's coinc_delta_hz
+ * (the simultaneous hits with close frequency pairs of Sec. 5 and Table 3).
+ * snr_a / snr_b: rho / sigma of the winners in channels 2 pair and
+ * 2 pair + 1 (FP32, sign kept). */
+typedef struct {
+  uint32_t pair;
+  uint32_t lag;
+  uint32_t template_a;
+  uint32_t template_b;
+  float snr_a;
+  float snr_b;
+} bfs_coinc;
 
 /* Plan descriptor.  All pointers are host memory, read during the call only. */
 typedef struct {
@@ -140,6 +167,12 @@ typedef struct {
                                    finite band kappa sigma < |rho| < kappa_hi sigma
                                    (the deep-search generalisation of Eq. 9 the
                                    paper proposes in Sec. 5) */
+  double coinc_delta_hz;        /* 0: none; > 0 (BFS_PLAN_PAIRS | BFS_PLAN_PROJECT
+                                   grid plans only): after the projection, every
+                                   lag where both channels of a pair have a hit
+                                   whose winning templates' initial frequencies
+                                   differ by less than this is listed as a
+                                   coincidence (Delta = 50 Hz in Sec. 5) */
 } bfs_plan_desc;
 
 /* Read-only facts about a plan. */
@@ -190,7 +223,8 @@ bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
  *          means every segment has length n.
  *   seg_offsets: host [n_segments], element offset of each segment from
  *          y_dev; NULL means the segments are packed back to back in order.
- *   n_segments: 1..65535.
+ *   n_segments: 1..65535 (BFS_PLAN_PAIRS: even, the two channels of each
+ *          pair of equal length, else BFS_ERR_INVALID_ARG).
  * Segments of one length form a group.  Per group: forward real FFT of each
  * segment (Eq. 5); then one fused kernel per (template, segment) computes
  * C = conj(W) Y, sigma by Parseval in FP64 (Eq. 7), the inverse FFT on chip
@@ -235,6 +269,16 @@ bfs_status bfsearch_fetch_tails(bfs_job* job, bfs_tail* out_host, uint64_t capac
  * bfsearch_fetch_tails likewise refuses projection plans. */
 bfs_status bfsearch_fetch_projection(bfs_job* job, bfs_peak* out_host, uint64_t capacity,
                                      uint64_t* n_written, uint64_t* n_total);
+
+/* Plans with coinc_delta_hz > 0: wait for the job and copy its coincidences
+ * (Sec. 5, Table 3: simultaneous hits of the two channels of a pair with
+ * close template frequencies) to out_host sorted by (pair, lag).  The device
+ * finds them from the per-lag projections of both channels, comparing the
+ * winners' initial frequencies in FP64.  *n_total = coincidences found;
+ * BFS_ERR_TAIL_OVERFLOW when it exceeds capacity (the first `capacity` in
+ * order are written).  BFS_ERR_INVALID_ARG for plans without a window. */
+bfs_status bfsearch_fetch_coincidences(bfs_job* job, bfs_coinc* out_host, uint64_t capacity,
+                                       uint64_t* n_written, uint64_t* n_total);
 
 /* Wait for the job and copy sigma[s][j] (FP64, Eq. 6 by Parseval) to out_host
  * ([n_segments][K] doubles). */

@@ -28,12 +28,15 @@ PLAN_GRAPH = 1
 PLAN_AUTOTUNE = 2
 PLAN_PROJECT = 4
 PLAN_SYMMETRIC = 8
+PLAN_PAIRS = 16
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
 TAIL_DTYPE = np.dtype(
     [("segment", "<u4"), ("template", "<u4"), ("lag", "<u4"), ("reserved", "<u4"), ("rho", "<f8")]
 )
 PEAK_DTYPE = np.dtype([("segment", "<u4"), ("lag", "<u4"), ("template", "<u4"), ("snr", "<f4")])
+COINC_DTYPE = np.dtype([("pair", "<u4"), ("lag", "<u4"), ("template_a", "<u4"), ("template_b", "<u4"),
+                        ("snr_a", "<f4"), ("snr_b", "<f4")])
 
 
 class PlanDesc(ctypes.Structure):
@@ -62,6 +65,7 @@ class PlanDesc(ctypes.Structure):
         ("candidate", ctypes.c_uint32),
         ("tile", ctypes.c_uint32),
         ("kappa_hi", ctypes.c_double),
+        ("coinc_delta_hz", ctypes.c_double),
     ]
 
 
@@ -107,6 +111,7 @@ def _load() -> ctypes.CDLL:
         "bfsearch_fetch_tails": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_sigma": [vp, vp],
         "bfsearch_fetch_projection": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "bfsearch_fetch_coincidences": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_job_timing": [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
         "bfsearch_job_release": [vp],
         "bfsearch_job_poll": [vp, ctypes.POINTER(ctypes.c_int)],
@@ -170,7 +175,8 @@ class Plan:
                  templates: np.ndarray | None = None, precision: str = "f32",
                  tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
                  n_min: int | None = None, graph: bool = False, autotune: bool = False,
-                 candidate: int = 0, tile: int = 0, project: bool = False, kappa_hi: float = 0.0):
+                 candidate: int = 0, tile: int = 0, project: bool = False, kappa_hi: float = 0.0,
+                 pairs: bool = False, coinc_delta_hz: float = 0.0):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
         d.n_min = int(n_min) if n_min else 0
@@ -180,6 +186,10 @@ class Plan:
         d.candidate = int(candidate)
         d.tile = int(tile)
         d.kappa_hi = float(kappa_hi)
+        d.coinc_delta_hz = float(coinc_delta_hz)
+        if pairs:
+            d.flags |= PLAN_PAIRS
+        self.pairs = bool(pairs)
         keep = []
         if templates is not None:
             t = np.ascontiguousarray(np.atleast_2d(np.asarray(templates, dtype=np.float64)))
@@ -265,7 +275,7 @@ class Plan:
 
         y: [S, n] for segments of the plan's largest length; or, with `lengths` (one power of
         two in [n_min, n] per segment), a flat tensor holding the segments back to back (or at
-        element `offsets`)."""
+        element `offsets`).  Pair plans: pair p's two channels are segments 2p and 2p + 1."""
         if lengths is None:
             y = self._segments(y)
             S, lens_p, offs_p, lens = y.shape[0], None, None, [self.n] * y.shape[0]
@@ -370,6 +380,18 @@ class Job:
                                             ctypes.byref(nt))
         if not (st == BFS_ERR_TAIL_OVERFLOW and allow_overflow):
             _check(st, "bfsearch_fetch_projection")
+        return out[: nw.value], nt.value
+
+    def fetch_coincidences(self, capacity: int | None = None, allow_overflow: bool = False):
+        """Coincidences of detector pairs (plans with a coincidence window): COINC_DTYPE records
+        sorted by (pair, lag), and the exact number found."""
+        cap = sum(self.lengths[0::2]) if capacity is None else int(capacity)
+        out = np.empty(cap, dtype=COINC_DTYPE)  # only the first n_written records are filled
+        nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
+        st = _lib.bfsearch_fetch_coincidences(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw),
+                                              ctypes.byref(nt))
+        if not (st == BFS_ERR_TAIL_OVERFLOW and allow_overflow):
+            _check(st, "bfsearch_fetch_coincidences")
         return out[: nw.value], nt.value
 
     def done(self) -> bool:

@@ -240,11 +240,6 @@ __global__ __launch_bounds__(256) void spectrum_export_kernel(const TW* __restri
   o[2 * k + 1] = im;
 }
 
-__global__ void fill_u64_kernel(unsigned long long* p, uint64_t n, unsigned long long v) {
-  const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 // ------------------------------------------------------------ correlation --
 // Stage 1: spectral product, Parseval partial sum and Hermitian repack of one
 // block of F::M bins, read from element row_off of the rows: the whole half
@@ -371,15 +366,20 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
 }
 
 // Stage 2: inverse transform of length F::M on chip.  Returns the workgroup
-// sum of every thread's acc, reduced in a fixed order (deterministic).
-template <class F, typename T>
+// sum of every thread's acc, reduced in a fixed order (deterministic); with
+// NACC = 2 also the sum of acc2 into *S2 (red then holds 2 F::NW doubles).
+template <class F, typename T, int NACC = 1>
 __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const uint32_t* cols,
                                             const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2, int t,
-                                            double acc) {
+                                            double acc, double acc2 = 0.0, double* S2 = nullptr) {
   fft3_pass1<F, +1>(v, tw1, cols);
   {
     const double ws = wave_sum(acc);
     if ((t & 63) == 0) red[t >> 6] = ws;
+    if constexpr (NACC == 2) {
+      const double ws2 = wave_sum(acc2);
+      if ((t & 63) == 0) red[F::NW + (t >> 6)] = ws2;
+    }
   }
   const Pass2Anchors<F, T> an2 = fft3_pass2_load<F, T>(tw2, t);
   fft3_ex1_write<F, 0>(v, lds, cols);
@@ -390,6 +390,13 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
   // formed here: otherwise the compiler defers the additions to the sum's
   // use and keeps the NW partial sums live through the transform
   asm volatile("" : "+v"(S));
+  if constexpr (NACC == 2) {
+    double Sb = 0.0;
+#pragma unroll
+    for (int w = 0; w < F::NW; ++w) Sb += red[F::NW + w];
+    asm volatile("" : "+v"(Sb));
+    *S2 = Sb;
+  }
   fft3_ex1_read<F, 0>(v, lds, t);
   lds_barrier();
   fft3_ex1_write<F, 1>(v, lds, cols);
@@ -487,35 +494,6 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_h
           tails[idx] = r;
         }
         ++idx;
-      }
-    }
-  }
-}
-
-// Projection keys -> list of (index, key) for every nonzero key (order
-// arbitrary; the host sorts), one atomicAdd per wave.  Entries past cap are
-// counted but not written.
-__global__ __launch_bounds__(256) void project_compact_kernel(const unsigned long long* __restrict__ keys, uint64_t n,
-                                                              unsigned long long* __restrict__ list,
-                                                              unsigned long long* __restrict__ counter, uint64_t cap) {
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
-  for (uint64_t base_i = uint64_t(blockIdx.x) * blockDim.x; base_i < n; base_i += stride) {
-    const uint64_t i = base_i + threadIdx.x;
-    const unsigned long long key = i < n ? keys[i] : 0ull;
-    const bool pred = key != 0ull;
-    const uint64_t mask = __ballot(pred);
-    if (!mask) continue;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (pred) {
-      const uint64_t idx = base + __popcll(mask & below);
-      if (idx < cap) {
-        list[2 * idx] = i;
-        list[2 * idx + 1] = key;
       }
     }
   }
@@ -705,6 +683,292 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
       emit_tails<F, T>(z_hi, uint32_t(H), thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
     }
   }
+}
+
+// ------------------------------------------------------------ detector pairs --
+// The two time-aligned channels a and b of a detector pair (H1 and L1) are
+// correlated with one template through one complex inverse transform: the
+// paper's packing of a pair into the real and imaginary parts of one complex
+// series (Sec. 3.2 step (i)).  With the half spectra (k = 0..M, M = N/2)
+//   C^a_k = conj(W_k) A_k,  C^b_k = conj(W_k) B_k      (C_0, C_M real),
+// the spectrum of z = N (rho^a + i rho^b) is Q_k = P_k = C^a_k + i C^b_k for
+// k <= M and Q_{N-k} = R_k = conj(C^a_k) + i conj(C^b_k).  Its length-N
+// inverse transform does not fit one workgroup's registers at N = 2^16, so it
+// is split by decimation in frequency over the output parity e:
+//   z_{2m+e} = sum_{k<M} A^e_k exp(2 pi i k m / M),
+//   A^e_k = (P_k + (-1)^e R_{M-k}) exp(2 pi i k e / N),
+// one workgroup per parity, each a length-M transform with the passes of a
+// single correlation.  Both workgroups of a (pair, template) read the same
+// spectra; they run back to back on one XCD, so the second reads from L2.
+//
+// pair_pre forms A^e in registers, one register pair (k2, R1-1-k2) at a time:
+// under MAP_MIRROR the bins M - k of a thread's two registers are held by
+// lane l ^ 32 at the other register of the pair, so the R values cross with
+// two lane swaps per register.  Column S1/2 (lane 32 of wave 0) pairs within
+// its own register pair.  Column 0 (lane 0 of wave 0) pairs bin S1 k2 with
+// S1 (R1 - k2), another register pair: that thread first forms P_k alone
+// (plus the Nyquist term at k = 0), keeps its R values in `stash`, and adds
+// the partner terms after the loop.
+template <class F, int G, int E, typename T, typename TW>
+__device__ __forceinline__ void pair_pre(cx<T>* v, double& acc_a, double& acc_b, const uint32_t* cols,
+                                         const rsrc_t& rW, const rsrc_t& rA, const rsrc_t& rB,
+                                         const cx<T>* __restrict__ tw_u, int t, cx<T>* stash) {
+  constexpr int NP = F::R1 / 2;       // register pairs per column
+  // register pairs per load group: three spectra per bin load ahead here, so
+  // more than two pairs in flight spill
+  constexpr int GP = G >= 4 ? 2 : 1;
+  static_assert(NP % GP == 0 && F::R1 % 2 == 0, "pair group size");
+  constexpr int NG = NP / GP;
+  constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
+  const int lane = t & 63;
+  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) {
+    const uint32_t col = cols[c];
+    const bool dc = (c == 0) && (col == 0u);
+    cx<T> bu = {T(1), T(0)};
+    if constexpr (E == 1) bu = tw_u[col];  // exp(2 pi i col / N)
+    TW lw[2][GP][2];
+    cx<T> la[2][GP][2], lb[2][GP][2];
+    auto issue = [&](int g, int buf) {
+#pragma unroll
+      for (int p = 0; p < GP; ++p) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int i = g * GP + p;
+          const uint32_t k2 = uint32_t(h ? F::R1 - 1 - i : i);
+          lw[buf][p][h] = buf_load<TW>(rW, col * SW, uint32_t(F::S1) * k2 * SW);
+          la[buf][p][h] = buf_load<cx<T>>(rA, col * SY, uint32_t(F::S1) * k2 * SY);
+          lb[buf][p][h] = buf_load<cx<T>>(rB, col * SY, uint32_t(F::S1) * k2 * SY);
+        }
+      }
+    };
+    issue(0, 0);
+    static_for<NG>([&](auto gc) {
+      constexpr int g = decltype(gc)::value;
+      if constexpr (g + 1 < NG) issue(g + 1, (g + 1) & 1);
+      static_for<GP>([&](auto pc) {
+        constexpr int p = decltype(pc)::value;
+        constexpr int i = g * GP + p;
+        constexpr int r1 = i, r2 = F::R1 - 1 - i;
+        cx<T> P[2], R[2];
+        cx<T> RM = {T(0), T(0)};  // R_M (the Nyquist term) of column 0
+        static_for<2>([&](auto hc) {
+          constexpr int h = decltype(hc)::value;
+          cx<T> wk = load_spec<TW, T>(&lw[g & 1][p][h], 0), ak = la[g & 1][p][h], bk = lb[g & 1][p][h];
+          T cma = T(0), cmb = T(0);
+          if constexpr (r1 == 0 && h == 0) {
+            // slot 0 of column 0 packs the real X_0 (.x) and X_M (.y)
+            cma = dc ? wk.y * ak.y : T(0);
+            cmb = dc ? wk.y * bk.y : T(0);
+            wk.y = dc ? T(0) : wk.y;
+            ak.y = dc ? T(0) : ak.y;
+            bk.y = dc ? T(0) : bk.y;
+          }
+          const cx<T> ca = cmulc(wk, ak), cb = cmulc(wk, bk);
+          double pa = 2.0 * (double(ca.x) * double(ca.x) + double(ca.y) * double(ca.y));
+          double pb = 2.0 * (double(cb.x) * double(cb.x) + double(cb.y) * double(cb.y));
+          if constexpr (r1 == 0 && h == 0) {
+            pa = dc ? double(ca.x) * double(ca.x) + double(cma) * double(cma) : pa;
+            pb = dc ? double(cb.x) * double(cb.x) + double(cmb) * double(cmb) : pb;
+            RM = {cma, cmb};
+          }
+          acc_a += pa;
+          acc_b += pb;
+          P[h] = {ca.x - cb.y, ca.y + cb.x};
+          R[h] = {ca.x + cb.y, cb.x - ca.y};
+        });
+        cx<T> X0, X1;  // R_{M-k} for the bins of registers r1 and r2
+        partner_pair(R[0], R[1], X0, X1);
+        if (c == 0 && wave0) {
+          if (lane == 32) {  // column S1/2: its partners are its own two registers
+            X0 = R[1];
+            X1 = R[0];
+          }
+          if (lane == 0) {  // column 0: the partner terms are added after the loop
+            X0 = r1 == 0 ? RM : cx<T>{T(0), T(0)};
+            X1 = cx<T>{T(0), T(0)};
+            stash[r1] = R[0];
+            stash[r2] = R[1];
+          }
+        }
+        if constexpr (E == 0) {
+          v[c * F::R1 + r1] = cadd(P[0], X0);
+          v[c * F::R1 + r2] = cadd(P[1], X1);
+        } else {
+          v[c * F::R1 + r1] = cmul(rot<r1, 2 * F::R1, +1>(bu), csub(P[0], X0));
+          v[c * F::R1 + r2] = cmul(rot<r2, 2 * F::R1, +1>(bu), csub(P[1], X1));
+        }
+        pin(v[c * F::R1 + r1]);
+        pin(v[c * F::R1 + r2]);
+      });
+      pin(acc_a);
+      pin(acc_b);
+      sched_fence();
+    });
+    if (c == 0 && wave0 && lane == 0) {
+      // column 0: bin S1 r pairs with bin S1 (R1 - r); exp(2 pi i S1 r / N) = exp(i pi r / R1)
+      static_for<F::R1 - 1>([&](auto rc) {
+        constexpr int r = decltype(rc)::value + 1;
+        const cx<T> x = stash[F::R1 - r];
+        if constexpr (E == 0)
+          v[r] = cadd(v[r], x);
+        else
+          v[r] = csub(v[r], rot<r, 2 * F::R1, +1>(x));
+      });
+    }
+    sched_fence();
+  }
+}
+
+// Stage 3 of a pair workgroup of parity E, threshold: register i holds
+// z = N (rho^a + i rho^b) at lag 2 n + E (n the output index).  Component x
+// is channel a (segment sa, threshold thr[0]), y is channel b.
+template <class F, int E, typename T>
+__device__ __forceinline__ void emit_pair_tails(const cx<T>* v, const T* thr, const T* thr_hi, bool any,
+                                                const uint32_t* seg, uint32_t j, double N,
+                                                tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter,
+                                                uint64_t cap, unsigned long long* const* prow, const double* rootS,
+                                                int t) {
+  const int lane = t & 63;
+  auto is_tail = [&](T val, int h) { return any && (fabs(val) > thr[h]) && (fabs(val) < thr_hi[h]); };
+  uint32_t cnt = 0;
+#pragma unroll
+  for (int i = 0; i < F::P; ++i) cnt += uint32_t(is_tail(v[i].x, 0)) + uint32_t(is_tail(v[i].y, 1));
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t o = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += o;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  if (total == 0) return;
+  unsigned long long base = 0;
+  if (lane == 0) base = atomicAdd(counter, (unsigned long long)total);
+  base = __shfl(base, 0, 64);
+  if (cnt == 0) return;
+  uint64_t idx = base + (incl - cnt);
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) {
+#pragma unroll
+    for (int mp = 0; mp < F::R3; ++mp) {
+      const uint32_t lag = 2u * uint32_t(fft3_out_index<F>(t, c, mp)) + uint32_t(E);
+      const cx<T> a = v[c * F::R3 + mp];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        T val = h ? a.y : a.x;
+        asm volatile("" : "+v"(val));
+        if (!is_tail(val, h)) continue;
+        if (prow[h]) {
+          const float snr = float(fabs(double(val)) / rootS[h]);
+          const unsigned long long key = (static_cast<unsigned long long>(__float_as_uint(snr)) << 32) |
+                                         (static_cast<unsigned long long>(0x7fffffffu - j) << 1) |
+                                         (val < T(0) ? 1ull : 0ull);
+          atomicMax(prow[h] + lag, key);
+        } else if (idx < cap) {
+          tail_rec r;
+          r.segment = seg[h];
+          r.template_id = j;
+          r.lag = lag;
+          r.reserved = 0;
+          r.rho = double(val) / N;
+          tails[idx] = r;
+        }
+        ++idx;
+      }
+    }
+  }
+}
+
+template <typename T, typename TW, class F, bool DENSE, int G, int E>
+__device__ __forceinline__ void pair_body(T* lds, double* red, cx<T>* stash, const rsrc_t& rW, const rsrc_t& rA,
+                                          const rsrc_t& rB, const uint32_t* seg, const uint32_t* prow_row, uint32_t jg,
+                                          const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1,
+                                          const cx<T>* __restrict__ tw2, double kappa, double kappa_hi,
+                                          double* __restrict__ sigma_out, uint32_t k_total, tail_rec* __restrict__ tails,
+                                          unsigned long long* __restrict__ counter, uint64_t cap,
+                                          unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off,
+                                          T* __restrict__ rho_dense, int t) {
+  constexpr int M = F::M;
+  constexpr double N = 2.0 * M;
+  cx<T> v[F::P];
+  double acc_a = 0.0, acc_b = 0.0;
+  uint32_t cols[F::C1];
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
+  pair_pre<F, G, E, T, TW>(v, acc_a, acc_b, cols, rW, rA, rB, tw_u, t, stash);
+  double Sb = 0.0;
+  const double Sa = corr_ifft<F, T, 2>(v, lds, red, cols, tw1, tw2, t, acc_a, acc_b, &Sb);
+  const double rootS[2] = {sqrt(Sa), sqrt(Sb)};
+  if (E == 0 && t == 0 && sigma_out) {
+    sigma_out[uint64_t(seg[0]) * k_total + jg] = rootS[0] / N;
+    sigma_out[uint64_t(seg[1]) * k_total + jg] = rootS[1] / N;
+  }
+  if constexpr (DENSE) {
+    const T inv = T(1.0 / N);
+    T* ra = rho_dense + (uint64_t(seg[0]) * k_total + jg) * uint64_t(2 * M);
+    T* rb = rho_dense + (uint64_t(seg[1]) * k_total + jg) * uint64_t(2 * M);
+#pragma unroll
+    for (int c = 0; c < F::C2; ++c) {
+#pragma unroll
+      for (int mp = 0; mp < F::R3; ++mp) {
+        const uint32_t lag = 2u * uint32_t(fft3_out_index<F>(t, c, mp)) + uint32_t(E);
+        ra[lag] = v[c * F::R3 + mp].x * inv;
+        rb[lag] = v[c * F::R3 + mp].y * inv;
+      }
+    }
+  } else {
+    const T thr[2] = {T(kappa * rootS[0]), T(kappa * rootS[1])};
+    const T thr_hi[2] = {kappa_hi > 0.0 ? T(kappa_hi * rootS[0]) : T(INFINITY),
+                         kappa_hi > 0.0 ? T(kappa_hi * rootS[1]) : T(INFINITY)};
+    T ma = T(0), mb = T(0);
+#pragma unroll
+    for (int i = 0; i < F::P; ++i) {
+      ma = fmax(ma, fabs(v[i].x));
+      mb = fmax(mb, fabs(v[i].y));
+    }
+    const bool any = (ma > thr[0] && rootS[0] > 0.0) || (mb > thr[1] && rootS[1] > 0.0);
+    if (__ballot(any)) {
+      unsigned long long* prow[2] = {proj ? proj + proj_off[prow_row[0]] : nullptr,
+                                     proj ? proj + proj_off[prow_row[1]] : nullptr};
+      emit_pair_tails<F, E, T>(v, thr, thr_hi, any, seg, jg, N, tails, counter, cap, prow, rootS, t);
+    }
+  }
+}
+
+// One workgroup per (template j, pair row r) in the order of tile_map over n_rows = 2 x pairs
+// rows: pair q = r / 2, parity e = r % 2; its channels are spectrum rows 2q (a) and 2q + 1 (b)
+// of yspec, with the segment ids seg_ids[2q], seg_ids[2q + 1] (or row0 + those rows).  Other
+// arguments as corr_kernel.
+template <typename T, typename TW, class F, bool DENSE, int G>
+__global__ __launch_bounds__(F::NT) void pair_kernel(
+    const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
+    const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
+    uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
+    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
+    T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
+  constexpr int M = F::M;
+  __shared__ T lds[F::LDS_ELEMS];
+  __shared__ double red[2 * F::NW];
+  __shared__ cx<T> stash[F::R1];
+  const int t = threadIdx.x;
+  uint32_t j, row;
+  if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
+  const uint32_t ra = row & ~1u, rb = ra + 1u;
+  const uint32_t seg[2] = {uint32_t(__builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[ra] : row0 + ra)),
+                           uint32_t(__builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[rb] : row0 + rb))};
+  const uint32_t prow_row[2] = {ra, rb};
+  const uint32_t jg = j0 + j;
+  const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
+  const rsrc_t rA = make_rsrc(yspec + uint64_t(ra) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
+  const rsrc_t rB = make_rsrc(yspec + uint64_t(rb) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
+  if (row & 1u)
+    pair_body<T, TW, F, DENSE, G, 1>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, tw2, kappa,
+                                     kappa_hi, sigma_out, k_total, tails, counter, cap, proj, proj_off, rho_dense, t);
+  else
+    pair_body<T, TW, F, DENSE, G, 0>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, tw2, kappa,
+                                     kappa_hi, sigma_out, k_total, tails, counter, cap, proj, proj_off, rho_dense, t);
 }
 
 }  // namespace bfs

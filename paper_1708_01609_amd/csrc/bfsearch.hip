@@ -15,184 +15,18 @@
 #include <vector>
 
 #include "bfsearch.h"
-#include "bfs_kernels.h"
+#include "bfs_kernelset.h"
+#include "bfs_runtime_kernels.h"
 #include "bfs_tail_sort.h"
 
 using namespace bfs;
 
 static_assert(sizeof(tail_rec) == sizeof(bfs_tail), "tail record layout");
 static_assert(sizeof(tail_sort_rec) == sizeof(bfs_tail), "tail record layout");
+static_assert(sizeof(coinc_rec) == sizeof(bfs_coinc), "coincidence record layout");
 
 namespace {
 
-// ---------------------------------------------------------------- kernels --
-// A kernel configuration per (real type, storage type, M = N/2): radices
-// R1*R2*R3 and threads per workgroup of the on-chip transform, whether the
-// length-M inverse transform runs as two halves (split, when M points do not
-// fit one workgroup's registers), and the load-group depth G of the product
-// stage.  Each M has a short list of candidates; the first is the default and
-// the autotuner may pick another by timing (see tune_size).
-struct FwdArgs {
-  const void* src;          // explicit templates [K][src_stride] (FP64)
-  uint64_t src_stride;
-  uint32_t src_len;
-  const uint64_t* seg_ptr;  // segment sources: device address of each item's samples
-  const double* f0;
-  const double* fdot;
-  const uint32_t* len;
-  double fs;
-  int taper;
-  uint32_t first;
-  const void* tw1;
-  const void* tw2;
-  void* out;
-  double* energy;
-};
-
-struct CorrArgs {
-  const void* bank;
-  const void* y;
-  const uint32_t* seg_ids;  // global segment id of each grid row (null: the row index)
-  const void* tw_u;
-  const void* tw1;
-  const void* tw2;
-  uint32_t K;
-  uint32_t tile;            // segments per tile of the workgroup order (1 <= tile <= rows)
-  double kappa;
-  double* sigma;
-  tail_rec* tails;
-  unsigned long long* counter;
-  uint64_t cap;
-  unsigned long long* proj;  // projection keys (null: tail list)
-  const uint64_t* proj_off;  // per grid row: offset of its lags in proj
-  double kappa_hi;           // > 0: upper edge of a finite tail band
-  void* rho;
-};
-
-struct KernelSet {
-  int R1, R2, R3, NT;
-  int FM;            // length of the on-chip transform
-  int M;             // N/2 (= FM, or 2 FM when split)
-  int split;
-  int G;             // load-group depth of the product stage
-  size_t real_size;  // sizeof(T)
-  size_t spec_size;  // bytes of one stored template spectrum element
-  hipError_t (*fwd)(int src, uint32_t batch, hipStream_t st, const FwdArgs& a);
-  hipError_t (*unpack_bank)(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
-                            const void* tw_u, uint64_t row_off);
-  hipError_t (*unpack_y)(uint32_t batch, hipStream_t st, const void* Z, void* out, const void* tw_u);
-  hipError_t (*corr)(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a);
-  hipError_t (*export_bank)(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first);
-  hipError_t (*export_y)(uint32_t count, hipStream_t st, const void* y, double* out);
-};
-
-template <typename T, typename TW, class F, int SPLIT, int G>
-struct Impl {
-  static constexpr int M = F::M * (SPLIT ? 2 : 1);
-  static hipError_t fwd(int src, uint32_t batch, hipStream_t st, const FwdArgs& a) {
-    const dim3 grid(batch * (SPLIT ? 2u : 1u)), block(F::NT);
-    const auto* t1 = static_cast<const cx<T>*>(a.tw1);
-    const auto* t2 = static_cast<const cx<T>*>(a.tw2);
-    auto* out = static_cast<cx<T>*>(a.out);
-    if (src == SRC_SAMPLES)
-      hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
-    else if (src == SRC_CHIRP)
-      hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
-    else if (src == SRC_CHIRP_SYM)
-      hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP_SYM>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
-    else
-      hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
-    return hipGetLastError();
-  }
-  static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
-                                const void* tw_u, uint64_t row_off) {
-    const dim3 grid((M / 2 + 1 + 255) / 256, batch);
-    hipLaunchKernelGGL((rfft_unpack_kernel<T, TW>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(Z),
-                       static_cast<TW*>(out), energy, static_cast<const cx<T>*>(tw_u), uint32_t(M), row_off, SPLIT);
-    return hipGetLastError();
-  }
-  static hipError_t unpack_y(uint32_t batch, hipStream_t st, const void* Z, void* out, const void* tw_u) {
-    const dim3 grid((M / 2 + 1 + 255) / 256, batch);
-    hipLaunchKernelGGL((rfft_unpack_kernel<T, cx<T>>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(Z),
-                       static_cast<cx<T>*>(out), static_cast<const double*>(nullptr),
-                       static_cast<const cx<T>*>(tw_u), uint32_t(M), uint64_t(0), SPLIT);
-    return hipGetLastError();
-  }
-  template <bool DENSE>
-  static void launch_corr(uint32_t blocks, const TW* bank, const cx<T>* y, const uint32_t* seg_ids,
-                          const uint64_t* proj_off, uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0,
-                          uint32_t row0, hipStream_t st, const CorrArgs& a) {
-    const auto* tu = static_cast<const cx<T>*>(a.tw_u);
-    const auto* t1 = static_cast<const cx<T>*>(a.tw1);
-    const auto* t2 = static_cast<const cx<T>*>(a.tw2);
-    T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
-    if constexpr (SPLIT)
-      hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
-                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
-                         a.kappa_hi, rho, j0, a.K, row0);
-    else
-      hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
-                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
-                         a.kappa_hi, rho, j0, a.K, row0);
-  }
-  // 1-D grids in the XCD-aware order of tile_map, 8 ceil(K/8) S workgroups in all.  A
-  // launch holds at most MAX_ITEMS work items (the dispatch's grid size is a 32-bit count
-  // of work items): larger jobs run as several launches over slices of the segment rows
-  // (each with every template), and of the bank too when one row alone is too large.
-  static constexpr uint64_t MAX_ITEMS = 1ull << 31;
-  static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    if (!S || !a.K) return hipErrorInvalidValue;
-    const uint64_t max_blocks = MAX_ITEMS / F::NT;
-    uint64_t kc = a.K;  // templates per launch: all, or a multiple of 8 that fits one row
-    if (8ull * ((kc + 7) / 8) > max_blocks) kc = (max_blocks / 8) * 8;
-    const auto* bank = static_cast<const TW*>(a.bank);
-    const auto* y = static_cast<const cx<T>*>(a.y);
-    for (uint64_t j0 = 0; j0 < a.K; j0 += kc) {
-      const uint32_t kn = uint32_t(std::min<uint64_t>(kc, a.K - j0));
-      const uint64_t per_row = 8ull * ((kn + 7) / 8);
-      const uint32_t rows = uint32_t(std::max<uint64_t>(1, std::min<uint64_t>(S, max_blocks / per_row)));
-      for (uint32_t r0 = 0; r0 < S; r0 += rows) {
-        const uint32_t rn = std::min(rows, S - r0);
-        const uint32_t tile = std::min<uint32_t>(std::max<uint32_t>(a.tile, 1u), rn);
-        const uint32_t blocks = uint32_t(per_row * rn);
-        const TW* bk = bank + j0 * uint64_t(M);
-        const cx<T>* yr = y + uint64_t(r0) * M;
-        const uint32_t* ids = a.seg_ids ? a.seg_ids + r0 : nullptr;
-        const uint64_t* po = a.proj_off ? a.proj_off + r0 : nullptr;
-        if (dense)
-          launch_corr<true>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
-        else
-          launch_corr<false>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-      }
-    }
-    return hipSuccess;
-  }
-  static hipError_t export_bank(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first) {
-    const dim3 grid((M + 1 + 255) / 256, count);
-    hipLaunchKernelGGL((spectrum_export_kernel<T, TW>), grid, dim3(256), 0, st, static_cast<const TW*>(bank), out,
-                       uint32_t(M), first, SPLIT);
-    return hipGetLastError();
-  }
-  static hipError_t export_y(uint32_t count, hipStream_t st, const void* y, double* out) {
-    const dim3 grid((M + 1 + 255) / 256, count);
-    hipLaunchKernelGGL((spectrum_export_kernel<T, cx<T>>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(y),
-                       out, uint32_t(M), uint64_t(0), SPLIT);
-    return hipGetLastError();
-  }
-  static const KernelSet* get() {
-    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW),
-                                 &fwd, &unpack_bank, &unpack_y, &corr, &export_bank, &export_y};
-    return &ks;
-  }
-};
-
-constexpr int MAX_CANDIDATES = 8;
 constexpr int N_TILES = 5;
 constexpr uint32_t TILES[N_TILES] = {1, 2, 4, 8, 16};
 
@@ -202,82 +36,12 @@ uint32_t default_tile(const KernelSet& ks) {
   return uint32_t(std::max<uint64_t>(1, (2ull << 20) / row));
 }
 
-struct Candidates {
-  const KernelSet* ks[MAX_CANDIDATES];
-  int count = 0;
-  template <typename T, typename TW, class F, int SPLIT, int G>
-  void add() {
-    if (count < MAX_CANDIDATES) ks[count++] = Impl<T, TW, F, SPLIT, G>::get();
-  }
-};
-
-template <typename T, typename TW>
-Candidates candidates_t(uint32_t m) {
-  constexpr bool F32 = std::is_same_v<T, float>;
-  Candidates c;
-  switch (m) {
-    case 512:
-      c.add<T, TW, Fft3<T, 8, 8, 8, 64>, 0, 4>();
-      c.add<T, TW, Fft3<T, 8, 8, 8, 64>, 0, 2>();
-      break;
-    case 1024:
-      c.add<T, TW, Fft3<T, 4, 16, 16, 64>, 0, 4>();
-      c.add<T, TW, Fft3<T, 4, 16, 16, 64>, 0, 2>();
-      break;
-    case 2048:
-      c.add<T, TW, Fft3<T, 8, 16, 16, 128>, 0, 4>();
-      c.add<T, TW, Fft3<T, 8, 16, 16, 128>, 0, 2>();
-      break;
-    case 4096:
-      c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 0, 4>();
-      c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 0, 2>();
-      if constexpr (F32) {
-        c.add<T, TW, Fft3<T, 16, 16, 16, 128>, 0, 4>();
-        c.add<T, TW, Fft3<T, 4, 32, 32, 128>, 0, 4>();
-      }
-      break;
-    case 8192:
-      if constexpr (F32) {
-        c.add<T, TW, Fft3<T, 8, 32, 32, 256>, 0, 4>();
-        c.add<T, TW, Fft3<T, 8, 32, 32, 256>, 0, 2>();
-        c.add<T, TW, Fft3<T, 32, 16, 16, 256>, 0, 4>();
-      } else {
-        c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 1, 4>();
-        c.add<T, TW, Fft3<T, 16, 16, 16, 256>, 1, 2>();
-      }
-      break;
-    case 16384:
-      if constexpr (F32) {
-        c.add<T, TW, Fft3<T, 16, 32, 32, 512>, 0, 4>();
-        c.add<T, TW, Fft3<T, 16, 32, 32, 512>, 0, 2>();
-      }
-      break;
-    case 32768:
-      if constexpr (F32) {
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 8>();
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 4>();
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 2>();
-      }
-      break;
-    case 65536:
-      if constexpr (F32) {
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 4>();
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 2>();
-        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 1, 8>();
-      }
-      break;
-    default:
-      break;
-  }
-  return c;
-}
-
 Candidates candidates(bfs_precision p, uint32_t m) {
   switch (p) {
-    case BFS_FP64: return candidates_t<double, cx<double>>(m);
-    case BFS_FP32: return candidates_t<float, cx<float>>(m);
-    case BFS_FP32_W16F: return candidates_t<float, __half2>(m);
-    case BFS_FP32_W16B: return candidates_t<float, bf16x2>(m);
+    case BFS_FP64: return candidates_f64(m);
+    case BFS_FP32: return candidates_f32(m);
+    case BFS_FP32_W16F: return candidates_w16f(m);
+    case BFS_FP32_W16B: return candidates_w16b(m);
   }
   return Candidates{};
 }
@@ -352,6 +116,7 @@ struct JobNeed {
   uint64_t sigma = 0;      // S * K doubles
   uint64_t meta = 0;       // segment table bytes
   uint64_t proj = 0;       // projection entries (sum of segment lengths; 0: tail list)
+  uint64_t coinc = 0;      // coincidence slots (sum of the pairs' lengths; 0: none)
 };
 
 struct JobBuffers {
@@ -365,6 +130,7 @@ struct JobBuffers {
   void* meta_host = nullptr;  // pinned host staging of the table
   unsigned long long* proj = nullptr;        // projection keys [sum of segment lengths]
   unsigned long long* plist = nullptr;       // compacted (index, key) pairs
+  coinc_rec* clist = nullptr;                // coincidences of detector pairs
   unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
   bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
   uint64_t tails_host_cap = 0;
@@ -411,6 +177,9 @@ struct bfs_plan {
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
   bool graph = false;
   bool project = false;  // per-lag max projection instead of the tail list
+  bool pairs = false;    // segments come as detector pairs (2p, 2p + 1)
+  double delta = 0.0;    // coincidence window (Hz); 0: none
+  double* f0_dev = nullptr;  // initial frequency of every template (coincidence plans)
   hipStream_t copy_stream = nullptr;
   hipStream_t capture_stream = nullptr;  // graph plans only
   std::mutex capture_mu;  // one capture at a time on capture_stream
@@ -470,7 +239,8 @@ bfs_status alloc_checked(void** p, uint64_t bytes) {
 void free_job_buffers(JobBuffers* b) {
   if (!b) return;
   for (void* q : {b->y, b->z, static_cast<void*>(b->sigma), static_cast<void*>(b->tails),
-                  static_cast<void*>(b->counter), b->meta, static_cast<void*>(b->proj), static_cast<void*>(b->plist)})
+                  static_cast<void*>(b->counter), b->meta, static_cast<void*>(b->proj), static_cast<void*>(b->plist),
+                  static_cast<void*>(b->clist)})
     if (q) (void)hipFree(q);
   if (b->meta_host) (void)hipHostFree(b->meta_host);
   if (b->count_host) (void)hipHostFree(b->count_host);
@@ -490,6 +260,7 @@ void free_plan(bfs_plan* p) {
     if (sp.bank) (void)hipFree(sp.bank);
     if (sp.tables) (void)hipFree(sp.tables);
   }
+  if (p->f0_dev) (void)hipFree(p->f0_dev);
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (hipStream_t cs : p->owned_streams) (void)hipStreamDestroy(cs);
@@ -508,7 +279,11 @@ bfs_status validate(const bfs_plan_desc* d) {
   if (d->tail_capacity < 1) return BFS_ERR_INVALID_ARG;
   if (d->precision < BFS_FP64 || d->precision > BFS_FP32_W16B) return BFS_ERR_INVALID_ARG;
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
-  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT | BFS_PLAN_SYMMETRIC))
+  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT | BFS_PLAN_SYMMETRIC | BFS_PLAN_PAIRS))
+    return BFS_ERR_INVALID_ARG;
+  if (!std::isfinite(d->coinc_delta_hz) || d->coinc_delta_hz < 0.0) return BFS_ERR_INVALID_ARG;
+  if (d->coinc_delta_hz > 0.0 && (!(d->flags & BFS_PLAN_PAIRS) || !(d->flags & BFS_PLAN_PROJECT) ||
+                                  d->explicit_templates))
     return BFS_ERR_INVALID_ARG;
   if (!std::isfinite(d->kappa_hi) || (d->kappa_hi != 0.0 && !(d->kappa_hi > d->kappa))) return BFS_ERR_INVALID_ARG;
   if (d->candidate > uint32_t(MAX_CANDIDATES)) return BFS_ERR_INVALID_ARG;
@@ -527,8 +302,11 @@ bfs_status validate(const bfs_plan_desc* d) {
       if (L < 1.0 || L > double(nmin)) return BFS_ERR_INVALID_ARG;
     }
   }
-  for (uint32_t n = nmin; n <= d->n; n <<= 1)
-    if (!pick_kernels(d->precision, n / 2)) return BFS_ERR_UNSUPPORTED;
+  for (uint32_t n = nmin; n <= d->n; n <<= 1) {
+    const KernelSet* ks = pick_kernels(d->precision, n / 2);
+    if (!ks) return BFS_ERR_UNSUPPORTED;
+    if ((d->flags & BFS_PLAN_PAIRS) && !ks->corr_pair) return BFS_ERR_UNSUPPORTED;
+  }
   return BFS_OK;
 }
 
@@ -747,11 +525,13 @@ bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
 }
 
 bool covers(const JobNeed& c, const JobNeed& n) {
-  return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta && c.proj >= n.proj;
+  return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta && c.proj >= n.proj &&
+         c.coinc >= n.coinc;
 }
 
 uint64_t need_bytes(const JobNeed& c, uint64_t cap) {
-  return c.ybytes + c.zbytes + c.sigma * sizeof(double) + cap * sizeof(tail_rec) + c.meta + 3 * 8 * c.proj + 256;
+  return c.ybytes + c.zbytes + c.sigma * sizeof(double) + cap * sizeof(tail_rec) + c.meta + 3 * 8 * c.proj +
+         c.coinc * sizeof(coinc_rec) + 256;
 }
 
 bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
@@ -773,6 +553,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
     c.sigma = std::max(c.sigma, b->cap.sigma);
     c.meta = std::max(c.meta, b->cap.meta);
     c.proj = std::max(c.proj, b->cap.proj);
+    c.coinc = std::max(c.coinc, b->cap.coinc);
   }
   uint64_t bytes = need_bytes(c, p->cap);
   if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) {
@@ -795,6 +576,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   if (st == BFS_OK) st = alloc_checked(&b->meta, c.meta);
   if (st == BFS_OK && c.proj) st = alloc_checked(reinterpret_cast<void**>(&b->proj), c.proj * 8);
   if (st == BFS_OK && c.proj) st = alloc_checked(reinterpret_cast<void**>(&b->plist), c.proj * 16);
+  if (st == BFS_OK && c.coinc) st = alloc_checked(reinterpret_cast<void**>(&b->clist), c.coinc * sizeof(coinc_rec));
   if (st == BFS_OK && (hipHostMalloc(&b->meta_host, c.meta ? c.meta : 256, hipHostMallocDefault) != hipSuccess ||
                        hipHostMalloc(reinterpret_cast<void**>(&b->count_host), 256, hipHostMallocDefault) !=
                            hipSuccess)) {
@@ -835,12 +617,20 @@ struct Layout {
   JobNeed need;
 };
 
+// Bytes of the segment table of S segments (see stage_table).
+uint64_t table_bytes(uint32_t S) { return uint64_t(S) * (3 * sizeof(uint64_t) + sizeof(uint32_t)) + sizeof(uint64_t); }
+
 bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layout& L) {
   L.seg_len.resize(S);
   for (uint32_t s = 0; s < S; ++s) {
     const uint32_t n = lens ? lens[s] : p->n_max;
     if (!size_plan(p, n)) return BFS_ERR_INVALID_ARG;
     L.seg_len[s] = n;
+  }
+  if (p->pairs) {  // channels 2q and 2q + 1 of every pair, of equal length
+    if (S & 1u) return BFS_ERR_INVALID_ARG;
+    for (uint32_t s = 0; s < S; s += 2)
+      if (L.seg_len[s] != L.seg_len[s + 1]) return BFS_ERR_INVALID_ARG;
   }
   uint64_t ybytes = 0, zbytes = 0, first = 0;
   for (int i = int(p->sizes.size()) - 1; i >= 0; --i) {
@@ -862,28 +652,35 @@ bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layo
   L.need.ybytes = ybytes;
   L.need.zbytes = zbytes;
   L.need.sigma = uint64_t(S) * p->K;
-  L.need.meta = uint64_t(S) * (2 * sizeof(uint64_t) + sizeof(uint32_t)) + 256;
+  L.need.meta = table_bytes(S) + 256;
   if (p->project)
     for (uint32_t s = 0; s < S; ++s) L.need.proj += L.seg_len[s];
+  if (p->delta > 0.0)
+    for (uint32_t s = 0; s < S; s += 2) L.need.coinc += L.seg_len[s];
   return BFS_OK;
 }
 
-// Fill the pinned segment table, per entry in group order: [S] device address
-// of the samples, [S] offset of the segment's lags in the projection keys
-// (segments back to back in the caller's order), [S] caller index.
+// Fill the pinned segment table: per entry in group order [S] device address
+// of the samples and [S] offset of the segment's lags in the projection keys
+// (segments back to back in the caller's order); [S + 1] those offsets in the
+// caller's order (the last is the total); per entry in group order [S] caller
+// index.
 void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, const Layout& L, void* host) {
   const uint32_t S = uint32_t(L.seg_len.size());
   auto* ptrs = static_cast<uint64_t*>(host);
   auto* poff = ptrs + S;
-  auto* ids = reinterpret_cast<uint32_t*>(poff + S);
+  auto* lag0c = poff + S;
+  auto* ids = reinterpret_cast<uint32_t*>(lag0c + S + 1);
   const size_t rs = p->sizes[0].ks->real_size;
   std::vector<uint64_t> off(S), lag0(S);
   uint64_t acc = 0;
   for (uint32_t s = 0; s < S; ++s) {
     off[s] = offs ? offs[s] : acc;
     lag0[s] = acc;
+    lag0c[s] = acc;
     acc += L.seg_len[s];
   }
+  lag0c[S] = acc;
   for (const Group& g : L.groups) {
     uint32_t k = g.first;
     for (uint32_t s = 0; s < S; ++s) {
@@ -901,15 +698,14 @@ void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, con
 bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, hipStream_t st) {
   const uint32_t S = uint32_t(L.seg_len.size());
   const bool project = p->project && !dense;
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(2), 0ull);
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(3), 0ull);
   HIP_TRY(hipGetLastError());
   if (project) {
     const uint64_t n = L.need.proj;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, b->proj, n, 0ull);
     HIP_TRY(hipGetLastError());
   }
-  const uint64_t tbytes = uint64_t(S) * (2 * sizeof(uint64_t) + sizeof(uint32_t));
-  HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, tbytes, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, table_bytes(S), hipMemcpyHostToDevice, st));
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
   char* ybase = static_cast<char*>(b->y);
   for (const Group& g : L.groups) {
@@ -936,7 +732,8 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   const bool project = p->project && !dense;
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
   const auto* dpoff = dptr + S;
-  const auto* dids = reinterpret_cast<const uint32_t*>(dpoff + S);
+  const auto* dlag0 = dpoff + S;
+  const auto* dids = reinterpret_cast<const uint32_t*>(dlag0 + S + 1);
   char* ybase = static_cast<char*>(b->y);
   if (with_events) HIP_TRY(hipEventRecord(b->ev[1], cs));
   for (const Group& g : L.groups) {
@@ -958,7 +755,7 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.proj = project ? b->proj : nullptr;
     c.proj_off = project ? dpoff + g.first : nullptr;
     c.rho = rho;
-    HIP_TRY(g.sp->ks->corr(dense, g.count, cs, c));
+    HIP_TRY(p->pairs ? g.sp->ks->corr_pair(dense, g.count, cs, c) : g.sp->ks->corr(dense, g.count, cs, c));
   }
   if (with_events) HIP_TRY(hipEventRecord(b->ev[2], cs));
   if (project) {
@@ -967,6 +764,14 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     hipLaunchKernelGGL(project_compact_kernel, dim3(blocks), dim3(256), 0, cs, b->proj, n, b->plist, b->counter + 1,
                        n);
     HIP_TRY(hipGetLastError());
+    if (p->delta > 0.0) {  // coincidences of the pairs' two projections
+      uint32_t nmax = 0;
+      for (uint32_t s = 0; s < S; ++s) nmax = std::max(nmax, L.seg_len[s]);
+      const dim3 grid((nmax + 255) / 256, S / 2);
+      hipLaunchKernelGGL(coinc_kernel, grid, dim3(256), 0, cs, b->proj, dlag0, p->f0_dev, p->delta, b->clist,
+                         b->counter + 2, L.need.coinc);
+      HIP_TRY(hipGetLastError());
+    }
   }
   return BFS_OK;
 }
@@ -1080,7 +885,7 @@ bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, vo
 // Copy the job's two counters (tails, projection entries) to the pinned host
 // copy; the job has finished.
 hipError_t read_counters(bfs_plan* p, JobBuffers* b) {
-  hipError_t e = hipMemcpyAsync(b->count_host, b->counter, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+  hipError_t e = hipMemcpyAsync(b->count_host, b->counter, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                 p->copy_stream);
   if (e == hipSuccess) e = hipStreamSynchronize(p->copy_stream);
   return e;
@@ -1222,6 +1027,9 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     p->plan_bytes += sp.bank_bytes + sp.tab_bytes;
     p->sizes.push_back(sp);
   }
+  p->pairs = (d->flags & BFS_PLAN_PAIRS) != 0;
+  p->delta = d->coinc_delta_hz;
+  if (p->delta > 0.0) p->plan_bytes += uint64_t(p->K) * sizeof(double);
   if (hipSetDevice(d->device) != hipSuccess) {
     (void)hipGetLastError();
     delete p;
@@ -1252,6 +1060,13 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     if (st != BFS_OK) break;
   }
   if (st == BFS_OK) st = build_banks(p, d);
+  if (st == BFS_OK && p->delta > 0.0) {  // initial frequency per template, for the coincidence window
+    std::vector<double> f0(p->K);
+    for (uint32_t j = 0; j < p->K; ++j) f0[j] = linspace_at(d->f0_lo, d->f0_hi, d->n_f0, j / d->n_fdot);
+    st = alloc_checked(reinterpret_cast<void**>(&p->f0_dev), uint64_t(p->K) * sizeof(double));
+    if (st == BFS_OK && hipMemcpy(p->f0_dev, f0.data(), f0.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
+      st = BFS_ERR_HIP;
+  }
   if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate && !d->tile)
     for (SizePlan& sp : p->sizes)
       if (st == BFS_OK) st = tune_size(p, sp);
@@ -1434,6 +1249,33 @@ bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t ca
   });
   const uint64_t nw = std::min<uint64_t>(count, capacity);
   if (nw) std::memcpy(out_host, peaks.data(), nw * sizeof(bfs_peak));
+  *n_written = nw;
+  *n_total = count;
+  return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
+}
+
+bfs_status bfsearch_fetch_coincidences(bfs_job* j, bfs_coinc* out_host, uint64_t capacity, uint64_t* n_written,
+                                       uint64_t* n_total) {
+  if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
+  bfs_plan* p = j->plan;
+  if (!(p->delta > 0.0)) return BFS_ERR_INVALID_ARG;
+  JobBuffers* b = j->buf;
+  if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
+  HIP_TRY(hipEventSynchronize(b->ev[b->done]));
+  HIP_TRY(read_counters(p, b));
+  const unsigned long long count = b->count_host[2];  // <= the pairs' lags, the list's size
+  std::vector<coinc_rec> list(count);
+  if (count) {
+    HIP_TRY(hipMemcpyAsync(list.data(), b->clist, count * sizeof(coinc_rec), hipMemcpyDeviceToHost, p->copy_stream));
+    HIP_TRY(hipStreamSynchronize(p->copy_stream));
+  }
+  std::sort(list.begin(), list.end(), [](const coinc_rec& a, const coinc_rec& c) {
+    return a.pair != c.pair ? a.pair < c.pair : a.lag < c.lag;
+  });
+  const uint64_t nw = std::min<uint64_t>(count, capacity);
+  for (uint64_t i = 0; i < nw; ++i)
+    out_host[i] = bfs_coinc{list[i].pair, list[i].lag, list[i].template_a, list[i].template_b, list[i].snr_a,
+                            list[i].snr_b};
   *n_written = nw;
   *n_total = count;
   return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;

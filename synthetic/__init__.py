@@ -13,8 +13,8 @@ from .strain import (
     unit_hann_chirp,
     Injection,
 )
-from .workloads import (Arrival, Workload, WORKLOADS, arrivals, get_workload, make_segment, make_segments,
-                        request_samples)
+from .workloads import (Arrival, Workload, WORKLOADS, arrivals, get_workload, make_pair, make_segment,
+                        make_segments, request_samples)
 
 __all__ = [
     "ENTROPY",
@@ -26,6 +26,7 @@ __all__ = [
     "WORKLOADS",
     "get_workload",
     "make_segment",
+    "make_pair",
     "make_segments",
     "Arrival",
     "arrivals",

@@ -131,6 +131,18 @@ def make_segment(w: Workload, segment_idx: int = 0, channel: int = 0) -> tuple[n
     return y, injections
 
 
+def make_pair(w: Workload, segment_idx: int = 0) -> tuple[np.ndarray, np.ndarray, list[Injection]]:
+    """Two time-aligned detector channels of one segment of workload w: channel 0 is
+    make_segment(w, segment_idx); channel 1 carries independent band-limited noise (its own
+    seed) plus the same injections at the same offsets, as a signal seen by both detectors."""
+    a, injections = make_segment(w, segment_idx, channel=0)
+    b = bandlimited_noise(len(a), w.fs, seeded_rng(w.config_id, 1, segment_idx, "noise"))
+    b = add_injections(b, injections, w.fs)
+    if w.dtype == "f32":
+        b = b.astype(np.float32)
+    return a, b, injections
+
+
 def make_segments(w: Workload, count: int | None = None, channel: int = 0):
     """List of (samples, injections) for segments 0..count-1 of workload w."""
     count = w.n_segments if count is None else count

@@ -48,6 +48,7 @@ def test_struct_layouts_match_header(bfs):
     assert ctypes.sizeof(bfs.PlanInfo) == 48
     assert bfs.TAIL_DTYPE.itemsize == 24
     assert bfs.PEAK_DTYPE.itemsize == 16
+    assert bfs.COINC_DTYPE.itemsize == 24
     # bfs_plan_desc field order as declared (spot-check offsets of the 64-bit fields)
     assert bfs.PlanDesc.fs.offset == 8
     assert bfs.PlanDesc.tail_capacity.offset % 8 == 0
@@ -87,11 +88,14 @@ def _desc(bfs, **kw):
     ("n_min", 3000),        # not a power of two
     ("n_min", 1 << 17),     # above n
     ("n_min", 2048),        # shorter than the 4096-sample templates
-    ("flags", 16),          # unknown flag
+    ("flags", 64),          # unknown flag
     ("kappa_hi", 4.0),      # band edge below kappa
     ("kappa_hi", float("inf")),
     ("candidate", 99),      # no such kernel candidate
     ("tile", 1 << 20),      # tile beyond the segment limit
+    ("coinc_delta_hz", 50.0),  # a coincidence window without pairs and projection
+    ("coinc_delta_hz", -1.0),
+    ("coinc_delta_hz", float("nan")),
 ])
 def test_plan_rejects_invalid_descriptor(bfs, field, value):
     d, keep = _desc(bfs, **{field: value})
@@ -119,7 +123,28 @@ def test_plan_rejects_template_longer_than_segment(bfs):
     assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
 
 
+def test_pair_plans_need_pairs_and_projection_for_a_window(bfs):
+    # a window needs pairs and projection together, and grid templates (their initial frequencies)
+    for flags in (bfs.PLAN_PAIRS, bfs.PLAN_PROJECT):
+        d, keep = _desc(bfs, flags=flags, coinc_delta_hz=50.0)
+        out = ctypes.c_void_p()
+        assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+    temps = np.ones((2, 16))
+    d, keep = _desc(bfs, flags=bfs.PLAN_PAIRS | bfs.PLAN_PROJECT, coinc_delta_hz=50.0)
+    d.explicit_templates = temps.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.n_explicit, d.explicit_len = 2, 16
+    out = ctypes.c_void_p()
+    assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_INVALID_ARG
+
+
 def test_plan_reports_unsupported_sizes(bfs):
+    # pairs at lengths whose transform is split (2^17 FP32, 2^14 FP64) are not built
+    for n, prec in ((1 << 17, bfs.FP32), (1 << 14, bfs.FP64)):
+        d, keep = _desc(bfs, n=n, precision=prec, flags=bfs.PLAN_PAIRS)
+        taus = np.array([0.1])
+        d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out = ctypes.c_void_p()
+        assert bfs.raw_library().bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_UNSUPPORTED
     for n, prec in ((1 << 18, bfs.FP32), (1 << 15, bfs.FP64), (1 << 9, bfs.FP32)):
         d, keep = _desc(bfs, n=n, precision=prec)
         taus = np.array([0.1])
@@ -147,4 +172,5 @@ def test_null_handles_are_rejected(bfs):
     assert lib.bfsearch_plan_kernel_info(None, 0, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_job_poll(None, None) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_fetch_projection(None, None, 0, ctypes.byref(nw), ctypes.byref(nt)) == bfs.BFS_ERR_INVALID_ARG
+    assert lib.bfsearch_fetch_coincidences(None, None, 0, ctypes.byref(nw), ctypes.byref(nt)) == bfs.BFS_ERR_INVALID_ARG
     assert lib.bfsearch_plan_job_bytes(None, None, 1, None) == bfs.BFS_ERR_INVALID_ARG

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from synthetic import get_workload, make_segment
-from tests.parity import TOL
+from tests.parity import TOL, tol_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -31,9 +31,13 @@ def bfs():
     return bfsearch
 
 
-def compare_projection(gpu, segs, temps, kappa, tol, out):
-    """gpu: PEAK_DTYPE records; out: oracle.search(...) result.  Returns (common, band_only)."""
+def compare_projection(gpu, segs, temps, kappa, tol, out, floor=None):
+    """gpu: PEAK_DTYPE records; out: oracle.search(...) result.  Returns (common, band_only).
+
+    tol is in units of sigma; with floor ([S, K] sigma_floor values) a template far outside the
+    data band has the tolerance tol * tol_scale(sigma, floor) / sigma in units of its sigma."""
     sig = out["sigma"]
+    tsig = tol * tol_scale(sig, floor) / sig  # [S, K] tolerance of rho / sigma
     orc = oracle.max_projection(out["tails"], sig)
     by_key = {}
     for s, j, n, r in zip(out["tails"]["segment"], out["tails"]["template"], out["tails"]["lag"], out["tails"]["rho"]):
@@ -52,19 +56,21 @@ def compare_projection(gpu, segs, temps, kappa, tol, out):
     o = {(int(s), int(n)): (int(j), float(v)) for s, n, j, v in zip(orc["segment"], orc["lag"], orc["template"], orc["snr"])}
     band = 0
     for key in o.keys() - g.keys():  # every oracle tail at this lag sits in the band
-        assert max(abs(v) for v in by_key[key].values()) <= kappa + tol, (key, by_key[key])
+        s = key[0]
+        assert all(abs(v) <= kappa + tsig[s, j] for j, v in by_key[key].items()), (key, by_key[key])
         band += 1
     for key in g.keys() - o.keys():  # the GPU's winner is a tail only within the band
         s, n = key
-        assert abs(snr_o(s, g[key][0], n)) >= kappa - tol, (key, g[key])
+        assert abs(snr_o(s, g[key][0], n)) >= kappa - tsig[s, g[key][0]], (key, g[key])
         band += 1
     for key in g.keys() & o.keys():
         s, n = key
         jg, vg = g[key]
         jo, vo = o[key]
-        assert abs(abs(vg) - abs(vo)) <= tol + 2e-6 * abs(vo), (key, g[key], o[key])
+        t = max(tsig[s, jg], tsig[s, jo])
+        assert abs(abs(vg) - abs(vo)) <= t + 2e-6 * abs(vo), (key, g[key], o[key])
         vj = snr_o(s, jg, n)
-        assert abs(vj) >= abs(vo) - tol - 2e-6 * abs(vo) and np.sign(vj) == np.sign(vg), (key, g[key], o[key], vj)
+        assert abs(vj) >= abs(vo) - t - 2e-6 * abs(vo) and np.sign(vj) == np.sign(vg), (key, g[key], o[key], vj)
     return len(g.keys() & o.keys()), band
 
 
