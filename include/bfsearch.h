@@ -48,7 +48,9 @@ typedef enum {
   BFS_ERR_OUT_OF_MEMORY = -2, /* HBM budget or device allocation exceeded; nothing kept */
   BFS_ERR_HIP = -3,           /* a HIP runtime call failed */
   BFS_ERR_TAIL_OVERFLOW = -4, /* more tails than capacity; totals stay exact */
-  BFS_ERR_UNSUPPORTED = -5    /* valid request outside the built kernel set */
+  BFS_ERR_UNSUPPORTED = -5,   /* valid request outside the built kernel set */
+  BFS_ERR_SCRATCH_LIMIT = -6  /* bfsearch_filter_noalloc: the segments' spectra do
+                                 not fit the fixed scratch area */
 } bfs_status;
 
 typedef enum {
@@ -244,6 +246,37 @@ bfs_status bfsearch_plan(const bfs_plan_desc* desc, bfs_plan** out);
 bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* seg_offsets,
                            const uint32_t* seg_lengths, uint32_t n_segments, void* hip_stream,
                            bfs_job** out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the hot
+ * path of bfsearch_filter with no allocation and no host synchronisation.
+ * It makes no hipMalloc, hipFree or allocating library call; the segment
+ * spectra live in a fixed scratch area of the library, 16 MiB per device
+ * (BFS_NOALLOC_SCRATCH_BYTES), held from the first plan on that device until
+ * the process ends.  Queued on hip_stream (NULL = the null stream); returns
+ * at once.
+ *   y_dev: n_segments segments of seg_len samples (0 = the plan's largest
+ *          length; an accepted length) packed back to back, float (double for
+ *          BFS_FP64 plans), caller device memory.
+ *   tails_dev: caller device memory for tail_capacity records of
+ *          bfs_tail (unsorted, in the order the kernels reserve them);
+ *          tails past tail_capacity are counted but not written.
+ *   count_dev: caller device memory, one uint64_t: set to 0 on the stream,
+ *          then to the exact number of tails found.
+ *   sigma_dev: caller device memory [n_segments][K] doubles, or NULL.
+ * The spectra need n_segments * seg_len * 4 bytes (FP32; FP64: 8), twice that
+ * at the lengths the library splits (2^17 FP32, 2^14 FP64); more than the
+ * scratch area is BFS_ERR_SCRATCH_LIMIT, before anything is queued.
+ * BFS_ERR_INVALID_ARG for projection plans, an odd count on pair plans, or
+ * a length the plan does not hold.  Every call on one device shares its
+ * scratch area, so calls whose work overlaps on the device (different
+ * streams without ordering between them) race and give wrong results; calls
+ * queued on one stream are ordered and safe.  Plans on other devices have
+ * their own area. */
+#define BFS_NOALLOC_SCRATCH_BYTES (16u << 20)
+bfs_status bfsearch_filter_noalloc(bfs_plan* plan, const void* y_dev, uint32_t seg_len, uint32_t n_segments,
+                                   void* tails_dev, uint64_t tail_capacity, uint64_t* count_dev, double* sigma_dev,
+                                   void* hip_stream);
 
 /* Gather the tails to the host (Sec. 3.3: only the hits above threshold
  * cross to the host, never the correlation output itself; this is the

@@ -22,6 +22,8 @@ BFS_ERR_OUT_OF_MEMORY = -2
 BFS_ERR_HIP = -3
 BFS_ERR_TAIL_OVERFLOW = -4
 BFS_ERR_UNSUPPORTED = -5
+BFS_ERR_SCRATCH_LIMIT = -6
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 FP64, FP32, FP32_W16F, FP32_W16B = 0, 1, 2, 3
 PLAN_GRAPH = 1
@@ -108,6 +110,7 @@ def _load() -> ctypes.CDLL:
     sigs = {
         "bfsearch_plan": [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)],
         "bfsearch_filter": [vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)],
+        "bfsearch_filter_noalloc": [vp, vp, u32, u32, vp, u64, vp, vp, vp],
         "bfsearch_fetch_tails": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_sigma": [vp, vp],
         "bfsearch_fetch_projection": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
@@ -299,6 +302,36 @@ class Plan:
                                     _stream_handle(stream), ctypes.byref(h)), "bfsearch_filter")
         return Job(self, h, y, lens)
 
+    def filter_noalloc(self, y, tails_out, count_out, sigma_out=None, stream=None) -> None:
+        """The hot path with no allocation and no host synchronisation (bfsearch_filter_noalloc):
+        queued on `stream` (default: current), returns at once.  y: [S, n_s] segments of one
+        accepted length; tails_out: caller device memory for the unsorted tail records (a uint8
+        tensor of capacity * TAIL_DTYPE.itemsize bytes); count_out: one int64 on the device, set to
+        the exact tail count; sigma_out: [S, K] float64 on the device, or None.  Calls that overlap
+        on one device share its scratch area and race; calls on one stream are ordered."""
+        import torch
+
+        y = self._check_tensor(y)
+        if y.dim() == 1:
+            y = y.unsqueeze(0)
+        s, n = y.shape
+        for t, dt in ((tails_out, torch.uint8), (count_out, torch.int64)):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+                raise TypeError(f"output buffers must be contiguous CUDA tensors of {dt}")
+        if count_out.numel() < 1:
+            raise ValueError("count_out needs one element")
+        cap = tails_out.numel() // TAIL_DTYPE.itemsize
+        sp = None
+        if sigma_out is not None:
+            if (not isinstance(sigma_out, torch.Tensor) or not sigma_out.is_cuda or sigma_out.dtype != torch.float64
+                    or not sigma_out.is_contiguous() or sigma_out.numel() < s * self.k):
+                raise TypeError("sigma_out must be a contiguous CUDA float64 tensor of S * K elements")
+            sp = ctypes.c_void_p(sigma_out.data_ptr())
+        _check(_lib.bfsearch_filter_noalloc(self._h, ctypes.c_void_p(y.data_ptr()), n, s,
+                                            ctypes.c_void_p(tails_out.data_ptr()), cap,
+                                            ctypes.c_void_p(count_out.data_ptr()), sp, _stream_handle(stream)),
+               "bfsearch_filter_noalloc")
+
     def correlate_dense(self, y, first: int = 0, count: int | None = None, stream=None):
         """Diagnostic: every rho value [S, count, n_s] (plan sample dtype) and sigma [S, count]
         (float64) for segments y [S, n_s] of one accepted length n_s, against the templates
@@ -436,6 +469,15 @@ class Job:
 
     def __exit__(self, *exc):
         self.release()
+
+
+def tails_from_device(tails_out, count: int) -> np.ndarray:
+    """Decode the first min(count, capacity) records of a filter_noalloc tail buffer (a uint8 tensor)
+    into a TAIL_DTYPE array, in device order."""
+    cap = tails_out.numel() // TAIL_DTYPE.itemsize
+    n = min(int(count), cap)
+    raw = tails_out[: n * TAIL_DTYPE.itemsize].cpu().numpy()
+    return raw.view(TAIL_DTYPE).copy()
 
 
 def status_string(status: int) -> str:

@@ -45,8 +45,8 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
 }
 
 // One forward transform per workgroup.  Segment items read their samples at
-// the device address seg_ptr[item]; explicit templates at src + item
-// src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
+// the device address seg_ptr[item], or at src + item src_stride (elements of
+// T) when seg_ptr is null; explicit templates at src + item src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
 // samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
 // The chirp source writes the FP64 sum of x^2 over the samples it made to
 // energy[b] (the unpack turns it into the unit-norm scale); SRC_CHIRP_SYM
@@ -112,7 +112,8 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
       }
     }
   } else {
-    const T* x = reinterpret_cast<const T*>(uintptr_t(seg_ptr[item]));
+    const T* x = seg_ptr ? reinterpret_cast<const T*>(uintptr_t(seg_ptr[item]))
+                         : static_cast<const T*>(src) + uint64_t(item) * src_stride;
     constexpr uint32_t SC = sizeof(cx<T>);
     const rsrc_t rx = make_rsrc(x, cs * uint32_t(F::M) * SC);
 #pragma unroll

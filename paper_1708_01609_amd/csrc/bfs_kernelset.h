@@ -22,7 +22,8 @@ namespace bfs {
 // stage.  Each M has a short list of candidates; the first is the default and
 // the autotuner may pick another by timing (see tune_size).
 struct FwdArgs {
-  const void* src;          // explicit templates [K][src_stride] (FP64)
+  const void* src;          // explicit templates [K][src_stride] (FP64); segments packed
+                            // back to back at src_stride samples when seg_ptr is null
   uint64_t src_stride;
   uint32_t src_len;
   const uint64_t* seg_ptr;  // segment sources: device address of each item's samples

@@ -191,6 +191,7 @@ struct bfs_plan {
   std::mutex stream_mu;
   std::vector<std::pair<hipStream_t, hipStream_t>> corr_streams;  // caller stream -> paired stream
   std::vector<hipStream_t> owned_streams;
+  void* scratch = nullptr;  // this device's no-allocation scratch area (device address)
   std::mutex mu;
   std::vector<JobBuffers*> pool;  // released buffer sets (still allocated on the device)
   uint64_t pool_bytes = 0;         // their device bytes
@@ -980,6 +981,39 @@ void sort_tails(bfs_tail* t, uint64_t n) {
   for (uint64_t i = 0; i < n; ++i) t[i] = tmp[idx[i]];
 }
 
+// ------------------------------------------------------------ no-allocation scratch --
+// The segment spectra (and the split length's transform scratch) of
+// bfsearch_filter_noalloc live in this array, one copy per device, held until
+// the process ends.  Host code never passes the array's name to a kernel: its
+// device address on each device comes from hipGetSymbolAddress (scratch_address)
+// and only that address is used.
+constexpr uint64_t NOALLOC_SCRATCH_BYTES = BFS_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device ordinal; null until looked up
+
+// The device address of `scratch` on `device`, which must be the current
+// device; looked up once per device.
+bfs_status scratch_address(int device, void** out) {
+  *out = nullptr;
+  if (device < 0) return BFS_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (size_t(device) < g_scratch_ptr.size() && g_scratch_ptr[size_t(device)]) {
+    *out = g_scratch_ptr[size_t(device)];
+    return BFS_OK;
+  }
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return BFS_ERR_HIP;
+  }
+  if (g_scratch_ptr.size() <= size_t(device)) g_scratch_ptr.resize(size_t(device) + 1, nullptr);
+  g_scratch_ptr[size_t(device)] = ptr;
+  *out = ptr;
+  return BFS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -992,6 +1026,7 @@ const char* bfsearch_status_string(bfs_status s) {
     case BFS_ERR_HIP: return "HIP runtime error";
     case BFS_ERR_TAIL_OVERFLOW: return "tail buffer overflow";
     case BFS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case BFS_ERR_SCRATCH_LIMIT: return "request exceeds the no-allocation scratch area";
   }
   return "unknown status";
 }
@@ -1040,6 +1075,9 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     delete p;
     return BFS_ERR_HIP;
   }
+  // the no-allocation entry point's scratch area on this device (looked up once per
+  // device; a failed lookup only disables that entry point)
+  if (scratch_address(d->device, &p->scratch) != BFS_OK) p->scratch = nullptr;
   p->budget = d->hbm_budget_bytes ? std::min<uint64_t>(d->hbm_budget_bytes, free_b) : free_b;
   if (p->plan_bytes > p->budget) {
     free_plan(p);
@@ -1153,6 +1191,59 @@ bfs_status bfsearch_filter(bfs_plan* p, const void* y_dev, const uint64_t* seg_o
   j->groups = std::move(L.groups);
   j->seg_len = std::move(L.seg_len);
   *out = j;
+  return BFS_OK;
+}
+
+bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_len, uint32_t S, void* tails_dev,
+                                   uint64_t tail_capacity, uint64_t* count_dev, double* sigma_dev, void* hip_stream) {
+  if (!p || !y_dev || !count_dev || S < 1 || S > 65535 || (tail_capacity && !tails_dev)) return BFS_ERR_INVALID_ARG;
+  if (p->project) return BFS_ERR_INVALID_ARG;
+  if (!seg_len) seg_len = p->n_max;
+  const SizePlan* sp = size_plan(p, seg_len);
+  if (!sp) return BFS_ERR_INVALID_ARG;
+  if (p->pairs && (S & 1u)) return BFS_ERR_INVALID_ARG;
+  const KernelSet& ks = *sp->ks;
+  // segment spectra, then (split length) the transform scratch
+  const uint64_t spec_bytes = uint64_t(S) * sp->M * 2 * ks.real_size;
+  const uint64_t y_bytes = (spec_bytes + 255) & ~uint64_t(255);
+  const uint64_t z_bytes = ks.split ? spec_bytes : 0;
+  if (y_bytes + z_bytes > NOALLOC_SCRATCH_BYTES) return BFS_ERR_SCRATCH_LIMIT;
+  if (!p->scratch) return BFS_ERR_HIP;
+  int cur = -1;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  char* y = static_cast<char*>(p->scratch);
+  void* z = ks.split ? y + y_bytes : nullptr;
+  auto* counter = reinterpret_cast<unsigned long long*>(count_dev);
+  // the count starts at zero (a fill kernel, so the call can be captured in a graph)
+  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, counter, uint64_t(1), 0ull);
+  HIP_TRY(hipGetLastError());
+  FwdArgs a{};
+  a.src = y_dev;
+  a.src_stride = seg_len;
+  a.seg_ptr = nullptr;  // segments packed back to back
+  a.tw1 = sp->tw1;
+  a.tw2 = sp->tw2;
+  a.out = ks.split ? z : y;
+  HIP_TRY(ks.fwd(SRC_SAMPLES, S, st, a));
+  HIP_TRY(ks.unpack_y(S, st, a.out, y, sp->tw_u));
+  CorrArgs c{};
+  c.bank = sp->bank;
+  c.y = y;
+  c.seg_ids = nullptr;  // row r is segment r
+  c.tw_u = sp->tw_u;
+  c.tw1 = sp->tw1;
+  c.tw2 = sp->tw2;
+  c.K = p->K;
+  c.tile = sp->tile;
+  c.kappa = p->kappa;
+  c.kappa_hi = p->kappa_hi;
+  c.sigma = sigma_dev;
+  c.tails = static_cast<tail_rec*>(tails_dev);
+  c.counter = counter;
+  c.cap = tail_capacity;
+  HIP_TRY(p->pairs ? ks.corr_pair(false, S, st, c) : ks.corr(false, S, st, c));
   return BFS_OK;
 }
 

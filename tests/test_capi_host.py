@@ -115,6 +115,14 @@ def test_plan_desc_layout_matches_header(bfs):
     assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4
 
 
+def test_noalloc_arguments_are_checked_on_the_host(bfs):
+    lib = bfs.raw_library()
+    count = ctypes.c_uint64()
+    assert lib.bfsearch_filter_noalloc(None, ctypes.c_void_p(16), 0, 1, None, 0, ctypes.byref(count), None,
+                                       None) == bfs.BFS_ERR_INVALID_ARG
+    assert "scratch" in bfs.status_string(bfs.BFS_ERR_SCRATCH_LIMIT)
+
+
 def test_plan_rejects_template_longer_than_segment(bfs):
     taus = np.array([2.0])  # 8192 samples > N = 4096
     d, _ = _desc(bfs, n=4096)
