@@ -68,9 +68,31 @@ def algorithmic_flops(n: int) -> float:
     return 2.5 * n * math.log2(n) + 6.0 * (n // 2 + 1) + n
 
 
+def fused_flops(n: int, length: float) -> float:
+    """Per correlation with fused synthesis: the resident path's work plus the template's forward
+    real FFT (2.5 N log2 N, its first radix-R pass pruned to the template's rows is not
+    discounted), the unpack to the real spectrum (10 per bin) and the synthesis of L samples
+    (the FP64 phase and taper are counted as 20 flops per sample)."""
+    return algorithmic_flops(n) + 2.5 * n * math.log2(n) + 10.0 * (n // 2) + 20.0 * length
+
+
 def algorithmic_bytes(n: int, spec_bytes: int) -> float:
     """Per correlation: one template spectrum row read from HBM (N/2 packed complex values)."""
     return (n // 2) * spec_bytes
+
+
+def roof(flops: float, hbm_bytes: float, seconds: float) -> dict:
+    """Achieved algorithmic FP32 VALU rate and HBM rate of `seconds` of kernel time, each as a
+    fraction of the MI355X peak (157.3 TFLOP/s FP32 vector, 8 TB/s HBM)."""
+    return {"achieved_tflops": flops / seconds / 1e12, "frac": flops / seconds / PEAK_FP32_VECTOR,
+            "hbm_achieved_GBps": hbm_bytes / seconds / 1e9, "hbm_frac": hbm_bytes / seconds / PEAK_HBM}
+
+
+SPEC_BYTES = {"f64": 16, "f32": 8, "f32-w16f": 4, "f32-w16b": 4}
+
+# steps keep running after the requested warm-ups until this much wall time has passed, so
+# the clocks reach their steady state whatever --warmup is
+MIN_WARMUP_S = 1.5
 
 
 def parse():
@@ -102,27 +124,34 @@ def parse():
 
 
 def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=False, symmetric=False, kappa=None,
-             kappa_hi=0.0):
+             kappa_hi=0.0, collect=None, pairs=False, fused=False):
     """Plan the workload, then time `steps` steps.  A step is one filter call (segment FFT +
     fused kernel over every template) and the fetch of its sorted tails; up to `depth` steps are
     queued on the stream, so the next step's kernels run while the host fetches and sorts the
     last one's tails (two concurrent streams measured slower: their kernels compete for the
-    CUs).  Every timed step completes inside the timed region."""
+    CUs).  Every timed step completes inside the timed region.  Warm-up runs the requested
+    steps and then goes on until MIN_WARMUP_S has passed.  collect = (first, count): after
+    timing, also return the dense rho and sigma of those templates and the last step's tails
+    (for the comparison with the oracle, outside the timed region)."""
     from collections import deque
+
+    import numpy as np
 
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus, symmetric=symmetric)
     t0 = time.perf_counter()
     plan = bfs.Plan(w.n, w.fs, kappa=w.kappa if kappa is None else kappa, grid=grid, precision=precision,
-                    tail_capacity=1 << 22, autotune=True, project=project, kappa_hi=kappa_hi)
+                    tail_capacity=1 << 22, autotune=True, project=project, kappa_hi=kappa_hi, pairs=pairs,
+                    fused=fused)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     kernel = plan.kernel_info()
-    corr_ms, job_ms, lat_ms, n_tails = [], [], [], 0
+    corr_ms, job_ms, lat_ms, n_tails, last = [], [], [], 0, [None]
 
     def finish(item):
         nonlocal n_tails
         job, ts = item
-        _, total = job.fetch_projection() if project else job.fetch_tails()
+        recs, total = job.fetch_projection() if project else job.fetch_tails()
+        last[0] = recs
         lat_ms.append((time.perf_counter() - ts) * 1e3)
         c, t = job.timing()
         corr_ms.append(c)
@@ -139,7 +168,10 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=Fa
         while q:
             finish(q.popleft())
 
+    tw = time.perf_counter()
     loop(warmup)
+    while time.perf_counter() - tw < MIN_WARMUP_S:
+        loop(max(depth, 8))
     torch.cuda.synchronize()
     corr_ms.clear(), job_ms.clear(), lat_ms.clear()
     t0 = time.perf_counter()
@@ -148,8 +180,38 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=Fa
     wall = time.perf_counter() - t0
     info = {"bank_bytes": plan.bank_bytes, "threads": plan.threads_per_correlation,
             "job_device_ms": float(sum(job_ms) / len(job_ms)), "kernel": kernel}
+    if collect is not None:
+        first, count = collect
+        rho, sig = [], []
+        for j0 in range(first, first + count, 1024):
+            c = min(1024, first + count - j0)
+            r, sg = plan.correlate_dense(y_dev[:1], first=j0, count=c)
+            rho.append(r[0].cpu().numpy())
+            sig.append(sg[0].cpu().numpy())
+        info["dense"] = {"first": first, "rho": np.concatenate(rho), "sigma": np.concatenate(sig),
+                         "tails": last[0], "kappa": w.kappa if kappa is None else kappa}
     plan.close()
     return wall, build_s, corr_ms, lat_ms, n_tails, info
+
+
+def run_pairs(bfs, torch, w, args):
+    """Detector pairs: the C2 segment (channel 0) and a second, independent channel of the same
+    shape correlated as one pair (both channels through one complex inverse transform per
+    template, Sec. 3.2 step (i)); a step is one filter call over the pair and its tail fetch."""
+    import numpy as np
+    from synthetic import make_segment
+
+    ys = np.stack([make_segment(w, 0, channel=c)[0] for c in (0, 1)]).astype(np.float32)
+    y_dev = torch.from_numpy(ys).cuda()
+    wall, build_s, corr_ms, _, n_tails, info = run_plan(bfs, torch, w, y_dev, args.precision, args.steps,
+                                                        args.warmup, args.depth, pairs=True)
+    k = w.n_templates
+    ks = float(np.mean(corr_ms)) * 1e-3
+    corr = 2 * k  # real correlations per step
+    return {"value": args.steps * corr / wall, "unit": "correlations/s", "kernel_rate": corr / ks,
+            "roofline": roof(algorithmic_flops(w.n) * corr, algorithmic_bytes(w.n, SPEC_BYTES[args.precision]) * k,
+                             ks),
+            "ms_per_step": wall / args.steps * 1e3, "tails_per_step": n_tails, "kernel": info["kernel"]}
 
 
 def run_batched(bfs, torch, steps, warmup):
@@ -201,32 +263,48 @@ def run_batched(bfs, torch, steps, warmup):
     corr = k * len(segs)
     flops = sum(algorithmic_flops(n) for n in lens) * k
     kernels = {str(n): plan.kernel_info(n) for n in sorted(set(lens))}
+    # per length: the chosen kernel's time per correlation as the autotuner measured it at plan
+    # build (HIP events around launches over 16 segments x 4096 templates in the chosen tile
+    # order); the bank row is read once per tile of segments
+    per_n = {}
+    for n, ki in kernels.items():
+        us = ki["tile_us"].get(ki["tile"], 0.0)
+        if us > 0:
+            per_n[n] = dict(roof(algorithmic_flops(int(n)), algorithmic_bytes(int(n), 8) / ki["tile"], us * 1e-6),
+                            us_per_correlation=us, tile=ki["tile"])
     out = {"workload": f"C4: {w.description}", "value": steps * corr / wall, "unit": "correlations/s",
            "ms_per_step": wall / steps * 1e3, "graph_replay_ms": float(np.mean(graph_ms)),
            "correlations_per_step": corr, "segment_lengths": {str(n): lens.count(n) for n in sorted(set(lens))},
            "achieved_tflops_algorithmic": flops / (np.mean(graph_ms) * 1e-3) / 1e12,
            "frac_of_fp32_vector_peak": flops / (np.mean(graph_ms) * 1e-3) / PEAK_FP32_VECTOR,
+           "roofline_per_n": per_n,
            "bank_bytes": plan.bank_bytes, "bank_build_and_tune_s": build_s, "tails_per_step": tails,
            "kernels": kernels}
     plan.close()
     return out
 
 
-def run_dense_bank(bfs, torch, steps, warmup):
-    """C3: the C2 segment against all 1,048,576 chirps (1024 f0 x 1024 fdot), kappa 5.5, with FP16
-    spectra resident (128 GiB; FP32 would take 256 GiB of the 288 GB)."""
+def run_dense_bank(bfs, torch, steps, warmup, precision="f32-w16f", collect=None, fused=False):
+    """C3: the C2 segment against all 1,048,576 chirps (1024 f0 x 1024 fdot), kappa 5.5: 16-bit
+    spectra resident (128 GiB), or FP32 with fused synthesis (each chirp made and transformed per
+    correlation; a resident FP32 bank would take 256 GiB of the 288 GB)."""
     import numpy as np
     from synthetic import get_workload, make_segment
 
     w = get_workload("C3")
     y, _ = make_segment(w, 0)
     y_dev = torch.from_numpy(np.ascontiguousarray(y[None, :])).to(device="cuda:0", dtype=torch.float32)
-    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, "f32-w16f", steps, warmup)
+    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, precision, steps, warmup,
+                                                             collect=collect, fused=fused)
     k = w.n_templates
-    return {"workload": f"C3: {w.description}", "precision": "f32-w16f", "value": steps * k / wall,
-            "unit": "correlations/s", "kernel_rate": k / (float(np.mean(corr_ms)) * 1e-3),
-            "ms_per_step": wall / steps * 1e3, "bank_bytes": info["bank_bytes"], "bank_build_s": build_s,
-            "tails_per_step": n_tails}
+    ks = float(np.mean(corr_ms)) * 1e-3
+    flops = (fused_flops(w.n, w.taus[0] * w.fs) if fused else algorithmic_flops(w.n)) * k
+    out = {"workload": f"C3: {w.description}", "precision": precision, "fused_synthesis": fused,
+           "value": steps * k / wall, "unit": "correlations/s", "kernel_rate": k / ks,
+           "roofline": roof(flops, 0.0 if fused else algorithmic_bytes(w.n, SPEC_BYTES[precision]) * k, ks),
+           "ms_per_step": wall / steps * 1e3, "bank_bytes": info["bank_bytes"], "bank_build_s": build_s,
+           "tails_per_step": n_tails}
+    return out, info.get("dense")
 
 
 def run_serving(bfs, torch, args):
@@ -259,11 +337,82 @@ def run_serving(bfs, torch, args):
     sat = serve(ex, [r for r in reqs if r.arrival < args.serve_compressed_seconds], slots=args.slots,
                 max_batch=args.max_batch, budget_bytes=budget, speed=args.serve_speed, progress=report)
     k = w.n_templates
+    sat_sum = sat.summary(k)
+    sat_reqs = [r for r in reqs if r.arrival < args.serve_compressed_seconds and r.rid in sat.results]
+    flops = sum(algorithmic_flops(len(r.samples)) for r in sat_reqs) * k
+    hbm = sum(algorithmic_bytes(len(r.samples), 4) for r in sat_reqs) * k
+    sat_sum["roofline_wall_clock"] = roof(flops, hbm, sat.wall_s) if sat.wall_s > 0 else None
     out = {"workload": f"C5: {w.description}", "bank_bytes": plan.bank_bytes, "bank_build_and_tune_s": build_s,
            "slots": args.slots, "max_batch": args.max_batch, "hbm_budget_bytes_jobs": budget,
            "realtime": dict(rt.summary(k), simulated_s=args.serve_seconds, speed=1.0),
-           "compressed": dict(sat.summary(k), simulated_s=args.serve_compressed_seconds, speed=args.serve_speed)}
+           "compressed": dict(sat_sum, simulated_s=args.serve_compressed_seconds, speed=args.serve_speed)}
     plan.close()
+    return out
+
+
+# Tolerance on |rho_gpu - rho_oracle| / sigma_oracle per precision form (the stated targets: FP32
+# path 1e-4 sigma, reduced-storage path 2e-3 sigma).  A template whose sigma lies below
+# RELAX * ||w|| rms(y) sits almost wholly outside the data band; FP32 rounding follows that input
+# scale, so there the scale of the bound is RELAX * ||w|| rms(y) instead of sigma.
+ERR_TOL = {"f64": 1e-9, "f32": 1e-4, "f32-w16f": 2e-3, "f32-w16b": 2e-3}
+RELAX = 0.1
+
+
+def error_vs_oracle(w, y, dense, precision, block=512):
+    """Compare one precision form's dense rho, sigma and filter-path tails (segment 0, templates
+    dense['first'] ..) with the FP64 oracle: the largest |rho error| / sigma and |sigma error| / sigma
+    over the templates held to the bound strictly, the relaxed ones apart, and the tail sets
+    (equal outside a +-tol band around kappa sigma).  Checker leg: runs the oracle, never timed."""
+    import numpy as np
+
+    import oracle
+
+    f0, fd, tau = w.template_params()
+    first, rho_g, sig_g = dense["first"], dense["rho"], dense["sigma"]
+    kappa, tails = dense["kappa"], dense["tails"]
+    count = len(sig_g)
+    tol = ERR_TOL[precision]
+    y64 = np.asarray(y, dtype=np.float64)
+    rms_y = float(np.sqrt(np.mean(y64 * y64)))
+    t0 = tails[tails["segment"] == 0]
+    t0 = t0[(t0["template"] >= first) & (t0["template"] < first + count)]
+    err, s_o, floor = np.empty(count), np.empty(count), np.empty(count)
+    n_or = n_common = n_band = n_out = 0
+    for b0 in range(0, count, block):
+        ids = list(range(first + b0, first + min(count, b0 + block)))
+        bank = oracle.template_bank(f0, fd, tau, w.fs, ids=ids)
+        rho_o = oracle.correlate_fft(y64, np.array(bank))
+        so = oracle.sigma_time(rho_o)
+        sl = slice(b0, b0 + len(ids))
+        err[sl] = np.max(np.abs(rho_g[sl].astype(np.float64) - rho_o), axis=1)
+        s_o[sl] = so
+        floor[sl] = [float(np.sqrt(np.dot(t, t))) * rms_y for t in bank]
+        lo = np.searchsorted(t0["template"], ids[0], side="left")
+        for r, j in enumerate(ids):
+            hi = np.searchsorted(t0["template"], j, side="right")
+            lags_g = set(int(v) for v in t0["lag"][lo:hi])
+            lo = hi
+            lags_o = set(int(v) for v in oracle.threshold_tails(rho_o[r], so[r], kappa))
+            n_or += len(lags_o)
+            n_common += len(lags_o & lags_g)
+            scale = max(so[r], RELAX * floor[b0 + r])
+            for lag in lags_o ^ lags_g:
+                if abs(abs(rho_o[r, lag]) - kappa * so[r]) <= tol * scale:
+                    n_band += 1
+                else:
+                    n_out += 1
+        del rho_o
+    rel = s_o < RELAX * floor
+    sig_err = np.abs(sig_g - s_o)
+    scale = np.maximum(s_o, RELAX * floor)
+    out = {"templates": f"{first}..{first + count - 1}", "precision": precision, "tol_sigma": tol,
+           "max_rho_err_over_sigma": float(np.max(err[~rel] / s_o[~rel])),
+           "max_sigma_err_over_sigma": float(np.max(sig_err[~rel] / s_o[~rel])),
+           "n_relaxed": int(rel.sum()),
+           "relaxed_max_rho_err_over_scale": float(np.max(err[rel] / scale[rel])) if rel.any() else None,
+           "tails_oracle": n_or, "tails_gpu": int(len(t0)), "tails_common": n_common,
+           "tails_differ_in_band": n_band, "tails_differ_outside_band": n_out}
+    out["meets_tol"] = bool(np.all(err <= tol * scale) and np.all(sig_err <= tol * scale) and n_out == 0)
     return out
 
 
@@ -324,13 +473,18 @@ def main():
     dt = torch.float64 if args.precision == "f64" else torch.float32
     y_dev = torch.from_numpy(np.ascontiguousarray(y[None, :])).to(device="cuda:0", dtype=dt)
 
-    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(bfs, torch, w, y_dev, args.precision,
-                                                             args.steps, args.warmup, args.depth)
+    check = not args.no_cpu_baseline and w.name == "C2"  # the checker leg compares with the oracle
+    dense = {}  # precision form -> (workload, segment, GPU outputs) for the checker leg
+    wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(
+        bfs, torch, w, y_dev, args.precision, args.steps, args.warmup, args.depth,
+        collect=(0, w.n_templates) if check else None)
+    if check:
+        dense[f"{w.name} {args.precision}"] = (w, y, info.pop("dense"), args.precision)
     k = w.n_templates
     value = args.steps * k / wall
     corr_avg_s = float(np.mean(corr_ms)) * 1e-3
-    spec_bytes = {"f64": 16, "f32": 8, "f32-w16f": 4, "f32-w16b": 4}[args.precision]
-    achieved = algorithmic_flops(w.n) * k / corr_avg_s
+    spec_bytes = SPEC_BYTES[args.precision]
+    r = roof(algorithmic_flops(w.n) * k, algorithmic_bytes(w.n, spec_bytes) * k, corr_avg_s)
     line = {
         "metric": "correlations/s (N=2^16, tau=1 s) on 1 MI355X",
         "value": value,
@@ -349,16 +503,18 @@ def main():
         "roofline": {
             "bound": "alu",
             "kernel": "corr_kernel (fused product, sigma, inverse FFT, threshold, compaction)",
-            "achieved": achieved / 1e12,
+            "achieved": r["achieved_tflops"],
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_VECTOR,
+            "frac": r["frac"],
             "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(args.precision)
             if w.name == "C2" else None,
             "flops_per_correlation": algorithmic_flops(w.n),
             "correlations_per_launch": k,
             "kernel_ms_avg": corr_avg_s * 1e3,
-            "hbm_algorithmic_GBps": algorithmic_bytes(w.n, spec_bytes) * k / corr_avg_s / 1e9,
+            "hbm_algorithmic_GBps": r["hbm_achieved_GBps"],
+            "hbm_frac": r["hbm_frac"],
+            "hbm_peak_GBps": PEAK_HBM / 1e9,
         },
         "kernel_rate": k / corr_avg_s,
         "nominal_tflops": nominal_flops(w.n) * value / 1e12,
@@ -372,11 +528,18 @@ def main():
         "tails_per_step": n_tails,
     }
     if not args.no_fp16 and args.precision == "f32":
-        wall16, build16, corr16, lat16, _, info16 = run_plan(bfs, torch, w, y_dev, "f32-w16f",
-                                                             args.steps, args.warmup, args.depth)
-        line["fp16_spectra"] = {"value": args.steps * k / wall16, "kernel_rate": k / (np.mean(corr16) * 1e-3),
-                                "ms_per_step": wall16 / args.steps * 1e3, "bank_build_s": build16,
-                                "bank_bytes": info16["bank_bytes"]}
+        # reduced-storage form: template spectra stored FP16 / BF16, FFT and accumulation FP32
+        for prec, key in (("f32-w16f", "fp16_spectra"), ("f32-w16b", "bf16_spectra")):
+            wall16, build16, corr16, _, _, info16 = run_plan(bfs, torch, w, y_dev, prec, args.steps, args.warmup,
+                                                             args.depth, collect=(0, k) if check else None)
+            ks16 = float(np.mean(corr16)) * 1e-3
+            line[key] = {"value": args.steps * k / wall16, "kernel_rate": k / ks16,
+                         "roofline": roof(algorithmic_flops(w.n) * k, algorithmic_bytes(w.n, 4) * k, ks16),
+                         "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(prec),
+                         "ms_per_step": wall16 / args.steps * 1e3, "bank_build_s": build16,
+                         "bank_bytes": info16["bank_bytes"]}
+            if check:
+                dense[f"{w.name} {prec}"] = (w, y, info16.pop("dense"), prec)
     if args.copy_calibration_mib:
         # plain kernels of known traffic for scaling the HBM counters: fill writes X bytes,
         # neg reads X and writes X, sum reads X
@@ -402,14 +565,38 @@ def main():
                                                 args.depth, kappa=3.0, kappa_hi=3.5)
         line["band_threshold"] = {"kappa": 3.0, "kappa_hi": 3.5, "value": args.steps * k / wallb,
                                   "kernel_rate": k / (np.mean(corrb) * 1e-3), "tails_per_step": n_band}
+        line["detector_pairs"] = run_pairs(bfs, torch, w, args)
+    if args.workload == "C2" and args.precision == "f32":
+        # fused synthesis on the C2 workload: the same search with no resident bank
+        wallf, buildf, corrf, _, _, infof = run_plan(bfs, torch, w, y_dev, "f32", args.steps, args.warmup,
+                                                     args.depth, collect=(0, k) if check else None, fused=True)
+        ksf = float(np.mean(corrf)) * 1e-3
+        line["fused_synthesis"] = {"value": args.steps * k / wallf, "kernel_rate": k / ksf,
+                                   "roofline": roof(fused_flops(w.n, w.taus[0] * w.fs) * k, 0.0, ksf),
+                                   "ms_per_step": wallf / args.steps * 1e3, "plan_build_s": buildf,
+                                   "bank_bytes": infof["bank_bytes"], "kernel": infof["kernel"]}
+        if check:
+            dense[f"{w.name} f32 fused"] = (w, y, infof.pop("dense"), "f32")
     if not args.no_dense_bank and args.workload == "C2":
-        line["dense_bank_fp16"] = run_dense_bank(bfs, torch, 3, 1)
+        for prec, key, fused in (("f32-w16f", "dense_bank_fp16", False), ("f32-w16b", "dense_bank_bf16", False),
+                                 ("f32", "dense_bank_fp32_fused", True)):
+            out, d3 = run_dense_bank(bfs, torch, 3, 1, precision=prec, collect=(0, 4096) if check else None,
+                                     fused=fused)
+            line[key] = out
+            if check:
+                dense[f"C3 {prec}{' fused' if fused else ''}"] = (get_workload("C3"),
+                                                                  make_segment(get_workload("C3"), 0)[0], d3, prec)
     if not args.no_batched and args.workload == "C2":
         line["batched"] = run_batched(bfs, torch, args.batched_steps, 1)
     if not args.no_serving and args.workload == "C2":
         line["serving"] = run_serving(bfs, torch, args)
     if not args.no_cpu_baseline:
+        # checker leg: the oracle timed on the host cores, and every precision form's error
+        # against it (outside every timed region)
         line["cpu_baseline"] = cpu_baseline(w, y, args.cpu_templates)
+        if dense:
+            line["error_vs_oracle"] = {name: error_vs_oracle(wd, yd, dd, prec)
+                                       for name, (wd, yd, dd, prec) in dense.items()}
     print(json.dumps(line), flush=True)
 
 

@@ -90,6 +90,18 @@ typedef enum {
                                  transform the library splits (2^17 FP32, 2^14
                                  FP64) are BFS_ERR_UNSUPPORTED */
 
+#define BFS_PLAN_FUSED 32u    /* fused synthesis: keep no template bank; each
+                                 correlation synthesises its chirp on chip (FP64
+                                 phase and taper), transforms it and goes on as
+                                 with a resident bank (Sec. 3.2 steps (ii)-(iv)
+                                 with step (ii) made per correlation).  Grid
+                                 plans of BFS_FP32 precision without
+                                 BFS_PLAN_PAIRS, at lengths 2^10, 2^13 and 2^16
+                                 (else BFS_ERR_UNSUPPORTED).  Such a plan whose
+                                 resident bank would exceed the HBM budget takes
+                                 this form without the flag.  bfsearch_plan_spectra
+                                 is BFS_ERR_UNSUPPORTED for it */
+
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
 
@@ -208,6 +220,9 @@ typedef struct {
   float tile_us[5];             /* measured microseconds per correlation for tiles
                                    1, 2, 4, 8, 16 on 16 segments (BFS_PLAN_AUTOTUNE),
                                    else 0 */
+  uint32_t fused;               /* 1: templates synthesised per correlation (no bank) */
+  uint32_t fused_rows;          /* fused: nonzero input rows of the forward
+                                   transform's first pass */
 } bfs_kernel_info;
 
 /* Build a plan: synthesises every template on the device (FP64 phase and

@@ -31,6 +31,7 @@ PLAN_AUTOTUNE = 2
 PLAN_PROJECT = 4
 PLAN_SYMMETRIC = 8
 PLAN_PAIRS = 16
+PLAN_FUSED = 32
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
 TAIL_DTYPE = np.dtype(
@@ -85,6 +86,8 @@ class KernelInfo(ctypes.Structure):
         ("tuned_us", ctypes.c_float * 8),
         ("tile", ctypes.c_uint32),
         ("tile_us", ctypes.c_float * 5),
+        ("fused", ctypes.c_uint32),
+        ("fused_rows", ctypes.c_uint32),
     ]
 
 
@@ -179,7 +182,7 @@ class Plan:
                  tail_capacity: int = 1 << 20, hbm_budget_bytes: int = 0, device: int = 0,
                  n_min: int | None = None, graph: bool = False, autotune: bool = False,
                  candidate: int = 0, tile: int = 0, project: bool = False, kappa_hi: float = 0.0,
-                 pairs: bool = False, coinc_delta_hz: float = 0.0):
+                 pairs: bool = False, coinc_delta_hz: float = 0.0, fused: bool = False):
         d = PlanDesc()
         d.n, d.fs, d.kappa = int(n), float(fs), float(kappa)
         d.n_min = int(n_min) if n_min else 0
@@ -192,6 +195,8 @@ class Plan:
         d.coinc_delta_hz = float(coinc_delta_hz)
         if pairs:
             d.flags |= PLAN_PAIRS
+        if fused:
+            d.flags |= PLAN_FUSED
         self.pairs = bool(pairs)
         keep = []
         if templates is not None:
@@ -232,7 +237,8 @@ class Plan:
         return {"n": ki.n, "radices": (ki.r1, ki.r2, ki.r3), "threads": ki.threads, "load_group": ki.load_group,
                 "split": bool(ki.split), "candidate": ki.candidate, "n_candidates": ki.n_candidates,
                 "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)],
-                "tile": ki.tile, "tile_us": {t: float(ki.tile_us[i]) for i, t in enumerate((1, 2, 4, 8, 16))}}
+                "tile": ki.tile, "tile_us": {t: float(ki.tile_us[i]) for i, t in enumerate((1, 2, 4, 8, 16))},
+                "fused": bool(ki.fused), "fused_rows": ki.fused_rows}
 
     def held_bytes(self) -> int:
         """Device bytes the plan holds now (plan memory, live jobs, pooled buffer sets)."""

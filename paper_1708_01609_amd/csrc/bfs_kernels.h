@@ -261,6 +261,55 @@ struct NoHook {
   __device__ void operator()(int, int) const {}
 };
 
+// The Hermitian repack of the product stage, in place on the registers of
+// every column c (twiddle get_bu(c) = exp(2 pi i k / N) of the column's first
+// bin, called once per column before its registers are repacked):
+//   Z_k = (C_k + conj C_{M-k}) + i exp(2 pi i k / N) (C_k - conj C_{M-k}).
+// cM: C_M (real) of column 0 under MAP_MIRROR.
+template <class F, int MAP, typename T, class BU>
+__device__ __forceinline__ void repack_mirror(cx<T>* v, T cM, int t, BU&& get_bu) {
+  constexpr bool HAS_DC = MAP == MAP_MIRROR;
+  const int lane = t & 63;
+  // wave-uniform (readfirstlane), so the other waves branch around the fixups
+  // instead of issuing them with an empty exec mask
+  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) {
+    const cx<T> buc = get_bu(c);
+    cx<T> carry = {T(0), T(0)};
+    static_for<F::R1 / 2>([&](auto kc) {
+      constexpr int r1 = decltype(kc)::value;
+      constexpr int r2 = F::R1 - 1 - r1;
+      const cx<T> A = v[c * F::R1 + r1], B = v[c * F::R1 + r2];
+      cx<T> PA, PB;
+      partner_pair(A, B, PA, PB);
+      if constexpr (HAS_DC) {
+        if (c == 0 && wave0) {
+          const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
+          const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
+          PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
+          PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
+          PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
+          PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
+          carry = B;
+        }
+      }
+      auto repack = [&](const cx<T>& ck, const cx<T>& cp, const cx<T>& tk) {
+        const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
+        const cx<T> bq = {ck.x - cp.x, ck.y + cp.y};  // C_k - conj C_{M-k}
+        const cx<T> u = cmul(tk, bq);
+        return cx<T>{a.x - u.y, a.y + u.x};
+      };
+      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(buc));
+      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(buc));
+      pin(v[c * F::R1 + r1]);
+      pin(v[c * F::R1 + r2]);
+      if constexpr (r1 % 4 == 3) sched_fence();
+    });
+    sched_fence();
+  }
+}
+
 template <class F, int MAP, int G, typename T, typename TW, bool EARLY_BU = false, class Hook = NoHook>
 __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* cols, const rsrc_t& rW,
                                          const rsrc_t& rY, uint32_t row_off, const cx<T>* __restrict__ tw_u,
@@ -325,45 +374,10 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
     });
   }
 
-  const int lane = t & 63;
-  // wave-uniform (readfirstlane), so the other waves branch around the fixups
-  // instead of issuing them with an empty exec mask
-  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
-#pragma unroll
-  for (int c = 0; c < F::C1; ++c) {
+  repack_mirror<F, MAP, T>(v, cM, t, [&](int c) {
     if constexpr (!EARLY_BU) bu[c] = tw_u[bu_mul * cols[c] + bu_add];
-    cx<T> carry = {T(0), T(0)};
-    static_for<F::R1 / 2>([&](auto kc) {
-      constexpr int r1 = decltype(kc)::value;
-      constexpr int r2 = F::R1 - 1 - r1;
-      const cx<T> A = v[c * F::R1 + r1], B = v[c * F::R1 + r2];
-      cx<T> PA, PB;
-      partner_pair(A, B, PA, PB);
-      if constexpr (HAS_DC) {
-        if (c == 0 && wave0) {
-          const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
-          const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
-          PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
-          PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
-          PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
-          PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
-          carry = B;
-        }
-      }
-      auto repack = [&](const cx<T>& ck, const cx<T>& cp, const cx<T>& tk) {
-        const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
-        const cx<T> bq = {ck.x - cp.x, ck.y + cp.y};  // C_k - conj C_{M-k}
-        const cx<T> u = cmul(tk, bq);
-        return cx<T>{a.x - u.y, a.y + u.x};
-      };
-      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(bu[c]));
-      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(bu[c]));
-      pin(v[c * F::R1 + r1]);
-      pin(v[c * F::R1 + r2]);
-      if constexpr (r1 % 4 == 3) sched_fence();
-    });
-    sched_fence();
-  }
+    return bu[c];
+  });
 }
 
 // Stage 2: inverse transform of length F::M on chip.  Returns the workgroup

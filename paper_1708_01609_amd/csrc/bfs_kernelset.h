@@ -10,7 +10,7 @@
 #include <algorithm>
 #include <type_traits>
 
-#include "bfs_kernels.h"
+#include "bfs_fused.h"
 
 namespace bfs {
 
@@ -57,6 +57,16 @@ struct CorrArgs {
   const uint64_t* proj_off;  // per grid row: offset of its lags in proj
   double kappa_hi;           // > 0: upper edge of a finite tail band
   void* rho;
+  // fused synthesis (corr_fused): grid parameters and unit-norm factors of every template,
+  // the sample rate, taper and symmetry, and the input rows of the pruned first pass
+  const double* f0;
+  const double* fdot;
+  const uint32_t* len;
+  const float* norm;
+  double fs;
+  int taper;
+  int sym;
+  uint32_t rows;
 };
 
 struct KernelSet {
@@ -76,6 +86,11 @@ struct KernelSet {
   hipError_t (*corr_pair)(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a);
   hipError_t (*export_bank)(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first);
   hipError_t (*export_y)(uint32_t count, hipStream_t st, const void* y, double* out);
+  // fused synthesis (FP32 cubic sets with load group 4; null otherwise): the correlation with
+  // each template made on chip, and the segment spectra's copy in the fused layout
+  hipError_t (*corr_fused)(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a);
+  hipError_t (*permute_y)(uint32_t count, hipStream_t st, const void* y, void* out);
+  int fused_rows_max;  // largest pruned first-pass row count built below the full R1
 };
 
 template <typename T, typename TW, class F, int SPLIT, int G>
@@ -114,7 +129,24 @@ struct Impl {
                        static_cast<const cx<T>*>(tw_u), uint32_t(M), uint64_t(0), SPLIT);
     return hipGetLastError();
   }
-  template <bool DENSE, bool PAIR>
+  // fused synthesis is built for FP32 cubic transforms with one column per thread, load group 4
+  static constexpr bool FUSED = !SPLIT && std::is_same_v<T, float> && std::is_same_v<TW, cx<T>> && G == 4 &&
+                                fused_shape<F>();
+  static constexpr int FUSED_NZ = F::R1 > 2 ? 2 : F::R1;  // the pruned first pass (rows < 2 S1)
+  enum Mode { MODE_SINGLE = 0, MODE_PAIR = 1, MODE_FUSED = 2 };
+  template <bool DENSE, int NZ>
+  static void launch_fused(uint32_t blocks, const cx<T>* y, const uint32_t* seg_ids, const uint64_t* proj_off,
+                           uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0, uint32_t row0, hipStream_t st,
+                           const CorrArgs& a) {
+    if constexpr (FUSED) {
+      hipLaunchKernelGGL((corr_fused_kernel<T, F, DENSE, G, NZ>), dim3(blocks), dim3(F::NT), 0, st, y, seg_ids,
+                         static_cast<const cx<T>*>(a.tw_u), static_cast<const cx<T>*>(a.tw1),
+                         static_cast<const cx<T>*>(a.tw2), a.f0 + j0, a.fdot + j0, a.len + j0, a.norm + j0, a.fs,
+                         a.taper, a.sym, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         a.kappa_hi, DENSE ? static_cast<T*>(a.rho) : nullptr, j0, a.K, row0);
+    }
+  }
+  template <bool DENSE, int MODE>
   static void launch_corr(uint32_t blocks, const TW* bank, const cx<T>* y, const uint32_t* seg_ids,
                           const uint64_t* proj_off, uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0,
                           uint32_t row0, hipStream_t st, const CorrArgs& a) {
@@ -122,7 +154,13 @@ struct Impl {
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
-    if constexpr (PAIR && !SPLIT)
+    constexpr bool PAIR = MODE == MODE_PAIR;
+    if constexpr (MODE == MODE_FUSED) {
+      if (a.rows <= uint32_t(FUSED_NZ))
+        launch_fused<DENSE, FUSED_NZ>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
+      else
+        launch_fused<DENSE, F::R1>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
+    } else if constexpr (PAIR && !SPLIT)
       hipLaunchKernelGGL((pair_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
@@ -140,8 +178,9 @@ struct Impl {
   // of work items): larger jobs run as several launches over slices of the segment rows
   // (each with every template), and of the bank too when one row alone is too large.
   static constexpr uint64_t MAX_ITEMS = 1ull << 31;
-  template <bool PAIR>
+  template <int MODE>
   static hipError_t corr_t(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
+    constexpr bool PAIR = MODE == MODE_PAIR;
     if (!S || !a.K || (PAIR && (S & 1u))) return hipErrorInvalidValue;
     const uint64_t max_blocks = MAX_ITEMS / F::NT;
     uint64_t kc = a.K;  // templates per launch: all, or a multiple of 8 that fits one row
@@ -157,14 +196,14 @@ struct Impl {
         const uint32_t rn = std::min(rows, S - r0);
         const uint32_t tile = std::min<uint32_t>(std::max<uint32_t>(a.tile, 1u), rn);
         const uint32_t blocks = uint32_t(per_row * rn);
-        const TW* bk = bank + j0 * uint64_t(M);
+        const TW* bk = bank ? bank + j0 * uint64_t(M) : nullptr;
         const cx<T>* yr = y + uint64_t(r0) * M;
         const uint32_t* ids = a.seg_ids ? a.seg_ids + r0 : nullptr;
         const uint64_t* po = a.proj_off ? a.proj_off + r0 : nullptr;
         if (dense)
-          launch_corr<true, PAIR>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+          launch_corr<true, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
         else
-          launch_corr<false, PAIR>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+          launch_corr<false, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }
@@ -172,10 +211,23 @@ struct Impl {
     return hipSuccess;
   }
   static hipError_t corr(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    return corr_t<false>(dense, S, st, a);
+    return corr_t<MODE_SINGLE>(dense, S, st, a);
   }
   static hipError_t corr_pair(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
-    return corr_t<true>(dense, S, st, a);
+    return corr_t<MODE_PAIR>(dense, S, st, a);
+  }
+  static hipError_t corr_fused(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a) {
+    if (!a.f0 || !a.fdot || !a.len || !a.norm || a.rows < 1 || a.rows > uint32_t(F::R1)) return hipErrorInvalidValue;
+    return corr_t<MODE_FUSED>(dense, S, st, a);
+  }
+  static hipError_t permute_y(uint32_t count, hipStream_t st, const void* y, void* out) {
+    if constexpr (FUSED) {
+      const dim3 grid((M + 255) / 256, count);
+      hipLaunchKernelGGL((fused_permute_kernel<T, F::R1>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(y),
+                         static_cast<cx<T>*>(out));
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
   }
   static hipError_t export_bank(uint32_t count, hipStream_t st, const void* bank, double* out, uint64_t first) {
     const dim3 grid((M + 1 + 255) / 256, count);
@@ -192,7 +244,8 @@ struct Impl {
   static const KernelSet* get() {
     static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW),
                                  &fwd, &unpack_bank, &unpack_y, &corr, SPLIT ? nullptr : &corr_pair, &export_bank,
-                                 &export_y};
+                                 &export_y, FUSED ? &corr_fused : nullptr, FUSED ? &permute_y : nullptr,
+                                 FUSED_NZ};
     return &ks;
   }
 };

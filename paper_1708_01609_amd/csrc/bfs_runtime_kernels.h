@@ -1,6 +1,7 @@
 // Kernels of the runtime that are not templates (one definition, in the
 // library's runtime source): filling counters, compacting projection keys,
-// finding coincidences of detector pairs.
+// finding coincidences of detector pairs, the unit-norm factors of fused
+// synthesis.
 #pragma once
 
 #include "bfs_kernels.h"
@@ -89,6 +90,30 @@ __global__ __launch_bounds__(256) void coinc_kernel(const unsigned long long* __
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const uint64_t idx = b0 + __popcll(mask & below);
   if (idx < cap) out[idx] = coinc_rec{p, uint32_t(n), ja, jb, sa, sb};
+}
+
+// FP64 energy sum_m w[m]^2 of each grid chirp (the unit-norm factor of the
+// fused kernel is 1 / sqrt of it, as the resident bank's unpack applies).
+// One workgroup per template; the samples are the chirp_sample values.
+__global__ __launch_bounds__(256) void chirp_norm_kernel(const double* __restrict__ f0, const double* __restrict__ fdot,
+                                                         const uint32_t* __restrict__ len, double fs, int taper,
+                                                         int sym, float* __restrict__ norm) {
+  __shared__ double red[4];
+  const uint32_t j = blockIdx.x;
+  const int L = int(len[j]);
+  double acc = 0.0;
+  for (int m = threadIdx.x; m < L; m += 256) {
+    double a = chirp_sample(m, L, f0[j], fdot[j], fs, taper);
+    if (sym) a += chirp_sample(L - 1 - m, L, f0[j], fdot[j], fs, taper);
+    acc += a * a;
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double e = red[0] + red[1] + red[2] + red[3];
+    norm[j] = e > 0.0 ? float(1.0 / sqrt(e)) : 0.0f;
+  }
 }
 
 }  // namespace bfs

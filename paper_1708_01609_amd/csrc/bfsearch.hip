@@ -163,6 +163,7 @@ struct SizePlan {
   const void* tw1 = nullptr;
   const void* tw2 = nullptr;
   uint64_t bank_bytes = 0, tab_bytes = 0;
+  uint32_t fused_rows = 0;  // fused plans: nonzero input rows of the forward transform's first pass
 };
 
 }  // namespace
@@ -178,6 +179,13 @@ struct bfs_plan {
   bool graph = false;
   bool project = false;  // per-lag max projection instead of the tail list
   bool pairs = false;    // segments come as detector pairs (2p, 2p + 1)
+  // fused synthesis (no resident bank): the grid parameters of every template
+  // (f0 [K] | fdot [K] doubles, len [K] u32) and their unit-norm factors [K]
+  bool fused = false;
+  void* fparams = nullptr;
+  float* fnorm = nullptr;
+  double fs = 0.0;
+  int taper = 0, sym = 0;
   double delta = 0.0;    // coincidence window (Hz); 0: none
   double* f0_dev = nullptr;  // initial frequency of every template (coincidence plans)
   hipStream_t copy_stream = nullptr;
@@ -206,6 +214,7 @@ struct Group {
   const SizePlan* sp = nullptr;
   uint32_t count = 0;
   uint64_t y_off = 0;     // byte offset of the group's spectra in the job's y buffer
+  uint64_t yf_off = 0;    // fused plans: byte offset of their copy in the fused layout
   uint32_t first = 0;     // index of the group's first entry in the segment table
 };
 
@@ -262,6 +271,8 @@ void free_plan(bfs_plan* p) {
     if (sp.tables) (void)hipFree(sp.tables);
   }
   if (p->f0_dev) (void)hipFree(p->f0_dev);
+  if (p->fparams) (void)hipFree(p->fparams);
+  if (p->fnorm) (void)hipFree(p->fnorm);
   if (p->copy_stream) (void)hipStreamDestroy(p->copy_stream);
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   for (hipStream_t cs : p->owned_streams) (void)hipStreamDestroy(cs);
@@ -269,6 +280,23 @@ void free_plan(bfs_plan* p) {
 }
 
 uint32_t n_min_of(const bfs_plan_desc* d) { return d->n_min ? d->n_min : d->n; }
+
+// The candidate of length n / 2 with a fused-synthesis kernel (or -1).
+int fused_candidate(bfs_precision p, uint32_t m) {
+  const Candidates c = candidates(p, m);
+  for (int i = 0; i < c.count; ++i)
+    if (c.ks[i]->corr_fused) return i;
+  return -1;
+}
+
+// Fused synthesis serves grid plans of FP32 precision, single segments, at
+// lengths whose transform has a fused kernel.
+bool fused_possible(const bfs_plan_desc* d) {
+  if (d->explicit_templates || d->precision != BFS_FP32 || (d->flags & BFS_PLAN_PAIRS)) return false;
+  for (uint32_t n = n_min_of(d); n <= d->n; n <<= 1)
+    if (fused_candidate(d->precision, n / 2) < 0) return false;
+  return true;
+}
 
 bfs_status validate(const bfs_plan_desc* d) {
   if (!d) return BFS_ERR_INVALID_ARG;
@@ -280,7 +308,8 @@ bfs_status validate(const bfs_plan_desc* d) {
   if (d->tail_capacity < 1) return BFS_ERR_INVALID_ARG;
   if (d->precision < BFS_FP64 || d->precision > BFS_FP32_W16B) return BFS_ERR_INVALID_ARG;
   if (d->taper > 1) return BFS_ERR_INVALID_ARG;
-  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT | BFS_PLAN_SYMMETRIC | BFS_PLAN_PAIRS))
+  if (d->flags & ~uint32_t(BFS_PLAN_GRAPH | BFS_PLAN_AUTOTUNE | BFS_PLAN_PROJECT | BFS_PLAN_SYMMETRIC | BFS_PLAN_PAIRS |
+                           BFS_PLAN_FUSED))
     return BFS_ERR_INVALID_ARG;
   if (!std::isfinite(d->coinc_delta_hz) || d->coinc_delta_hz < 0.0) return BFS_ERR_INVALID_ARG;
   if (d->coinc_delta_hz > 0.0 && (!(d->flags & BFS_PLAN_PAIRS) || !(d->flags & BFS_PLAN_PROJECT) ||
@@ -308,6 +337,7 @@ bfs_status validate(const bfs_plan_desc* d) {
     if (!ks) return BFS_ERR_UNSUPPORTED;
     if ((d->flags & BFS_PLAN_PAIRS) && !ks->corr_pair) return BFS_ERR_UNSUPPORTED;
   }
+  if ((d->flags & BFS_PLAN_FUSED) && !fused_possible(d)) return BFS_ERR_UNSUPPORTED;
   return BFS_OK;
 }
 
@@ -525,6 +555,77 @@ bfs_status build_banks(bfs_plan* p, const bfs_plan_desc* d) {
   return out;
 }
 
+// Per accepted length: the kernel set, tile and bytes of the plan; with fused
+// synthesis no bank is kept (the candidate with a fused kernel, the grid
+// parameters and unit-norm factors instead).
+void size_plans(bfs_plan* p, const bfs_plan_desc* d, bool fused) {
+  p->sizes.clear();
+  p->fused = fused;
+  p->bank_bytes = 0;
+  p->plan_bytes = 0;
+  uint32_t lmax = 0;
+  if (!d->explicit_templates)
+    for (uint32_t i = 0; i < d->n_tau; ++i) lmax = std::max(lmax, uint32_t(std::nearbyint(d->tau[i] * d->fs)));
+  for (uint32_t n = p->n_min; n <= p->n_max; n <<= 1) {
+    SizePlan sp;
+    sp.N = n;
+    sp.M = n / 2;
+    const Candidates c = candidates(d->precision, sp.M);
+    sp.cand = (d->candidate && int(d->candidate) <= c.count) ? int(d->candidate) - 1 : 0;
+    if (fused) sp.cand = fused_candidate(d->precision, sp.M);
+    sp.ks = c.ks[sp.cand];
+    sp.n_cand = c.count;
+    sp.tile = d->tile ? d->tile : default_tile(*sp.ks);
+    sp.bank_bytes = fused ? 0 : uint64_t(p->K) * sp.M * sp.ks->spec_size;
+    if (fused) {
+      const uint32_t s1 = uint32_t(sp.ks->R2 * sp.ks->R3);
+      sp.fused_rows = std::max<uint32_t>(1, ((lmax + 1) / 2 + s1 - 1) / s1);
+    }
+    for (int i = 0; i < c.count; ++i)
+      sp.tab_bytes = std::max<uint64_t>(sp.tab_bytes, table_elems(*c.ks[i]) * c.ks[i]->real_size);
+    p->bank_bytes += sp.bank_bytes;
+    p->plan_bytes += sp.bank_bytes + sp.tab_bytes;
+    p->sizes.push_back(sp);
+  }
+  if (fused) p->plan_bytes += uint64_t(p->K) * (2 * sizeof(double) + sizeof(uint32_t) + sizeof(float));
+}
+
+// Fused plans: the grid parameters of every template on the device, and each
+// template's unit-norm factor 1 / sqrt(sum w^2) from its FP64 samples.
+bfs_status build_fused(bfs_plan* p, const bfs_plan_desc* d) {
+  const uint32_t K = p->K;
+  std::vector<double> f0(K), fdot(K);
+  std::vector<uint32_t> len(K);
+  for (uint32_t j = 0; j < K; ++j) {
+    f0[j] = linspace_at(d->f0_lo, d->f0_hi, d->n_f0, j / d->n_fdot);
+    fdot[j] = linspace_at(d->fdot_lo, d->fdot_hi, d->n_fdot, j % d->n_fdot);
+    len[j] = uint32_t(std::nearbyint(d->tau[j % d->n_tau] * d->fs));
+  }
+  p->fs = d->fs;
+  p->taper = int(d->taper);
+  p->sym = (d->flags & BFS_PLAN_SYMMETRIC) ? 1 : 0;
+  bfs_status st = alloc_checked(&p->fparams, uint64_t(K) * (2 * sizeof(double) + sizeof(uint32_t)));
+  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&p->fnorm), uint64_t(K) * sizeof(float));
+  if (st != BFS_OK) return st;
+  char* base = static_cast<char*>(p->fparams);
+  hipStream_t s = p->copy_stream;
+  HIP_TRY(hipMemcpyAsync(base, f0.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + K * sizeof(double), fdot.data(), K * sizeof(double), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(base + 2ull * K * sizeof(double), len.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  const auto* df0 = reinterpret_cast<const double*>(base);
+  const auto* dfd = df0 + K;
+  const auto* dlen = reinterpret_cast<const uint32_t*>(df0 + 2ull * K);
+  constexpr uint32_t CHUNK = 1u << 24;  // templates per launch (one workgroup each)
+  for (uint32_t j0 = 0; j0 < K; j0 += CHUNK) {
+    const uint32_t nb = std::min(CHUNK, K - j0);
+    hipLaunchKernelGGL(chirp_norm_kernel, dim3(nb), dim3(256), 0, s, df0 + j0, dfd + j0, dlen + j0, p->fs, p->taper,
+                       p->sym, p->fnorm + j0);
+    HIP_TRY(hipGetLastError());
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+  return BFS_OK;
+}
+
 bool covers(const JobNeed& c, const JobNeed& n) {
   return c.ybytes >= n.ybytes && c.zbytes >= n.zbytes && c.sigma >= n.sigma && c.meta >= n.meta && c.proj >= n.proj &&
          c.coinc >= n.coinc;
@@ -650,6 +751,10 @@ bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layo
     first += cnt;
     L.groups.push_back(g);
   }
+  if (p->fused) {  // a second copy of every group's spectra, in the fused layout
+    for (Group& g : L.groups) g.yf_off = ybytes + g.y_off;
+    ybytes *= 2;
+  }
   L.need.ybytes = ybytes;
   L.need.zbytes = zbytes;
   L.need.sigma = uint64_t(S) * p->K;
@@ -719,8 +824,22 @@ bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     a.out = ks.split ? b->z : yg;
     HIP_TRY(ks.fwd(SRC_SAMPLES, g.count, st, a));
     HIP_TRY(ks.unpack_y(g.count, st, a.out, yg, g.sp->tw_u));
+    if (p->fused) HIP_TRY(ks.permute_y(g.count, st, yg, ybase + g.yf_off));
   }
   return BFS_OK;
+}
+
+// The fused-synthesis fields of a correlation launch.
+void set_fused_args(const bfs_plan* p, const SizePlan& sp, CorrArgs& c) {
+  const auto* f0 = static_cast<const double*>(p->fparams);
+  c.f0 = f0;
+  c.fdot = f0 + p->K;
+  c.len = reinterpret_cast<const uint32_t*>(f0 + 2ull * p->K);
+  c.norm = p->fnorm;
+  c.fs = p->fs;
+  c.taper = p->taper;
+  c.sym = p->sym;
+  c.rows = sp.fused_rows;
 }
 
 // Queue the second part on cs: one fused correlation kernel per group, then
@@ -739,8 +858,9 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   if (with_events) HIP_TRY(hipEventRecord(b->ev[1], cs));
   for (const Group& g : L.groups) {
     CorrArgs c{};
-    c.bank = static_cast<const char*>(g.sp->bank) + uint64_t(first) * g.sp->M * g.sp->ks->spec_size;
-    c.y = ybase + g.y_off;
+    c.bank = p->fused ? nullptr
+                      : static_cast<const char*>(g.sp->bank) + uint64_t(first) * g.sp->M * g.sp->ks->spec_size;
+    c.y = ybase + (p->fused ? g.yf_off : g.y_off);
     c.seg_ids = dids + g.first;
     c.tw_u = g.sp->tw_u;
     c.tw1 = g.sp->tw1;
@@ -756,7 +876,18 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.proj = project ? b->proj : nullptr;
     c.proj_off = project ? dpoff + g.first : nullptr;
     c.rho = rho;
-    HIP_TRY(p->pairs ? g.sp->ks->corr_pair(dense, g.count, cs, c) : g.sp->ks->corr(dense, g.count, cs, c));
+    if (p->fused) {
+      set_fused_args(p, *g.sp, c);
+      if (first) {  // a slice of the bank: its templates' parameters
+        c.f0 += first;
+        c.fdot += first;
+        c.len += first;
+        c.norm += first;
+      }
+      HIP_TRY(g.sp->ks->corr_fused(dense, g.count, cs, c));
+    } else {
+      HIP_TRY(p->pairs ? g.sp->ks->corr_pair(dense, g.count, cs, c) : g.sp->ks->corr(dense, g.count, cs, c));
+    }
   }
   if (with_events) HIP_TRY(hipEventRecord(b->ev[2], cs));
   if (project) {
@@ -1046,22 +1177,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   p->kappa = d->kappa;
   p->kappa_hi = d->kappa_hi;
   p->cap = d->tail_capacity;
-  for (uint32_t n = p->n_min; n <= p->n_max; n <<= 1) {
-    SizePlan sp;
-    sp.N = n;
-    sp.M = n / 2;
-    const Candidates c = candidates(d->precision, sp.M);
-    sp.cand = (d->candidate && int(d->candidate) <= c.count) ? int(d->candidate) - 1 : 0;
-    sp.ks = c.ks[sp.cand];
-    sp.n_cand = c.count;
-    sp.tile = d->tile ? d->tile : default_tile(*sp.ks);
-    sp.bank_bytes = uint64_t(p->K) * sp.M * sp.ks->spec_size;
-    for (int i = 0; i < c.count; ++i)
-      sp.tab_bytes = std::max<uint64_t>(sp.tab_bytes, table_elems(*c.ks[i]) * c.ks[i]->real_size);
-    p->bank_bytes += sp.bank_bytes;
-    p->plan_bytes += sp.bank_bytes + sp.tab_bytes;
-    p->sizes.push_back(sp);
-  }
+  size_plans(p, d, (d->flags & BFS_PLAN_FUSED) != 0);
   p->pairs = (d->flags & BFS_PLAN_PAIRS) != 0;
   p->delta = d->coinc_delta_hz;
   if (p->delta > 0.0) p->plan_bytes += uint64_t(p->K) * sizeof(double);
@@ -1079,6 +1195,8 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   // device; a failed lookup only disables that entry point)
   if (scratch_address(d->device, &p->scratch) != BFS_OK) p->scratch = nullptr;
   p->budget = d->hbm_budget_bytes ? std::min<uint64_t>(d->hbm_budget_bytes, free_b) : free_b;
+  // a resident bank that does not fit falls back to fused synthesis where that serves the plan
+  if (p->plan_bytes > p->budget && !p->fused && fused_possible(d)) size_plans(p, d, true);
   if (p->plan_bytes > p->budget) {
     free_plan(p);
     return BFS_ERR_OUT_OF_MEMORY;
@@ -1092,12 +1210,12 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   }
   bfs_status st = BFS_OK;
   for (SizePlan& sp : p->sizes) {
-    st = alloc_checked(&sp.bank, sp.bank_bytes);
+    if (!p->fused) st = alloc_checked(&sp.bank, sp.bank_bytes);
     if (st == BFS_OK) st = alloc_checked(&sp.tables, sp.tab_bytes);
     if (st == BFS_OK) st = set_tables(sp, sp.ks);
     if (st != BFS_OK) break;
   }
-  if (st == BFS_OK) st = build_banks(p, d);
+  if (st == BFS_OK) st = p->fused ? build_fused(p, d) : build_banks(p, d);
   if (st == BFS_OK && p->delta > 0.0) {  // initial frequency per template, for the coincidence window
     std::vector<double> f0(p->K);
     for (uint32_t j = 0; j < p->K; ++j) f0[j] = linspace_at(d->f0_lo, d->f0_hi, d->n_f0, j / d->n_fdot);
@@ -1105,7 +1223,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     if (st == BFS_OK && hipMemcpy(p->f0_dev, f0.data(), f0.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess)
       st = BFS_ERR_HIP;
   }
-  if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate && !d->tile)
+  if (st == BFS_OK && (d->flags & BFS_PLAN_AUTOTUNE) && !d->candidate && !d->tile && !p->fused)
     for (SizePlan& sp : p->sizes)
       if (st == BFS_OK) st = tune_size(p, sp);
   if (st != BFS_OK) {
@@ -1150,6 +1268,8 @@ bfs_status bfsearch_plan_kernel_info(const bfs_plan* p, uint32_t n, bfs_kernel_i
   for (int i = 0; i < MAX_CANDIDATES && i < 8; ++i) out->tuned_us[i] = sp->tuned_us[i];
   out->tile = sp->tile;
   for (int i = 0; i < N_TILES; ++i) out->tile_us[i] = sp->tile_us[i];
+  out->fused = p->fused ? 1u : 0u;
+  out->fused_rows = sp->fused_rows;
   return BFS_OK;
 }
 
@@ -1203,10 +1323,11 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   if (!sp) return BFS_ERR_INVALID_ARG;
   if (p->pairs && (S & 1u)) return BFS_ERR_INVALID_ARG;
   const KernelSet& ks = *sp->ks;
-  // segment spectra, then (split length) the transform scratch
+  // segment spectra, then their fused-layout copy (fused plans) or (split length) the
+  // transform scratch
   const uint64_t spec_bytes = uint64_t(S) * sp->M * 2 * ks.real_size;
   const uint64_t y_bytes = (spec_bytes + 255) & ~uint64_t(255);
-  const uint64_t z_bytes = ks.split ? spec_bytes : 0;
+  const uint64_t z_bytes = (ks.split || p->fused) ? spec_bytes : 0;
   if (y_bytes + z_bytes > NOALLOC_SCRATCH_BYTES) return BFS_ERR_SCRATCH_LIMIT;
   if (!p->scratch) return BFS_ERR_HIP;
   int cur = -1;
@@ -1214,7 +1335,7 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   char* y = static_cast<char*>(p->scratch);
-  void* z = ks.split ? y + y_bytes : nullptr;
+  void* z = (ks.split || p->fused) ? y + y_bytes : nullptr;
   auto* counter = reinterpret_cast<unsigned long long*>(count_dev);
   // the count starts at zero (a fill kernel, so the call can be captured in a graph)
   hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, counter, uint64_t(1), 0ull);
@@ -1228,9 +1349,10 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   a.out = ks.split ? z : y;
   HIP_TRY(ks.fwd(SRC_SAMPLES, S, st, a));
   HIP_TRY(ks.unpack_y(S, st, a.out, y, sp->tw_u));
+  if (p->fused) HIP_TRY(ks.permute_y(S, st, y, z));
   CorrArgs c{};
   c.bank = sp->bank;
-  c.y = y;
+  c.y = p->fused ? z : y;
   c.seg_ids = nullptr;  // row r is segment r
   c.tw_u = sp->tw_u;
   c.tw1 = sp->tw1;
@@ -1243,7 +1365,12 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   c.tails = static_cast<tail_rec*>(tails_dev);
   c.counter = counter;
   c.cap = tail_capacity;
-  HIP_TRY(p->pairs ? ks.corr_pair(false, S, st, c) : ks.corr(false, S, st, c));
+  if (p->fused) {
+    set_fused_args(p, *sp, c);
+    HIP_TRY(ks.corr_fused(false, S, st, c));
+  } else {
+    HIP_TRY(p->pairs ? ks.corr_pair(false, S, st, c) : ks.corr(false, S, st, c));
+  }
   return BFS_OK;
 }
 
@@ -1473,6 +1600,7 @@ bfs_status bfsearch_plan_spectra(const bfs_plan* p, uint32_t n, uint32_t first, 
   if (!p || !out_dev || count < 1 || uint64_t(first) + count > p->K || count > 65535) return BFS_ERR_INVALID_ARG;
   const SizePlan* sp = size_plan(p, n ? n : p->n_max);
   if (!sp) return BFS_ERR_INVALID_ARG;
+  if (p->fused) return BFS_ERR_UNSUPPORTED;  // no resident bank
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(sp->ks->export_bank(count, static_cast<hipStream_t>(hip_stream), sp->bank, out_dev, first));
   return BFS_OK;

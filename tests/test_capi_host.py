@@ -112,7 +112,28 @@ def test_plan_desc_layout_matches_header(bfs):
     assert off["flags"] == off["device"] + 4 and off["candidate"] == off["flags"] + 4
     assert off["tile"] == off["candidate"] + 4 and off["kappa_hi"] % 8 == 0 and off["kappa_hi"] > off["tile"]
     assert ctypes.sizeof(bfs.PlanDesc) % 8 == 0
-    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4
+    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4 + 2 * 4
+
+
+def test_fused_plans_are_checked_on_the_host(bfs):
+    # fused synthesis needs grid templates, FP32 precision, single segments and a length with a
+    # fused kernel (2^10, 2^13, 2^16); anything else is refused before the device is touched
+    lib = bfs.raw_library()
+    cases = [dict(n=1 << 16, precision=bfs.FP64), dict(n=1 << 14), dict(n=1 << 17),
+             dict(n=1 << 16, flags=bfs.PLAN_PAIRS)]
+    for kw in cases:
+        flags = bfs.PLAN_FUSED | kw.pop("flags", 0)
+        d, keep = _desc(bfs, flags=flags, **kw)
+        taus = np.array([0.1])
+        d.tau = taus.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        out = ctypes.c_void_p()
+        assert lib.bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_UNSUPPORTED, kw
+    temps = np.ones((2, 16))
+    d, keep = _desc(bfs, n=1 << 16, flags=bfs.PLAN_FUSED)
+    d.explicit_templates = temps.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.n_explicit, d.explicit_len = 2, 16
+    out = ctypes.c_void_p()
+    assert lib.bfsearch_plan(ctypes.byref(d), ctypes.byref(out)) == bfs.BFS_ERR_UNSUPPORTED
 
 
 def test_noalloc_arguments_are_checked_on_the_host(bfs):

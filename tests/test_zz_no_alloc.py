@@ -38,19 +38,20 @@ def _key(t):
     return np.lexsort((t["lag"], t["template"], t["segment"]))
 
 
-CASES = [("f32", 1 << 14, False, (5, 3)), ("f32", 1 << 16, False, (3, 1)), ("f32", 1 << 17, False, (4, 2)),
-         ("f64", 1 << 13, False, (3, 2)), ("f64", 1 << 14, False, (2, 1)),
-         ("f32", 1 << 14, True, (4, 2))]
+CASES = [("f32", 1 << 14, "", (5, 3)), ("f32", 1 << 16, "", (3, 1)), ("f32", 1 << 17, "", (4, 2)),
+         ("f64", 1 << 13, "", (3, 2)), ("f64", 1 << 14, "", (2, 1)),
+         ("f32", 1 << 14, "pairs", (4, 2)), ("f32", 1 << 16, "fused", (2, 1))]
 
 
-@pytest.mark.parametrize("prec,n,pairs,counts", CASES,
-                         ids=[f"{p}-N{n}{'-pairs' if q else ''}" for p, n, q, _ in CASES])
-def test_noalloc_matches_filter(bfs, prec, n, pairs, counts):
+@pytest.mark.parametrize("prec,n,form,counts", CASES, ids=[f"{p}-N{n}{'-' + f if f else ''}" for p, n, f, _ in CASES])
+def test_noalloc_matches_filter(bfs, prec, n, form, counts):
+    pairs = form == "pairs"
     grid = bfs.Grid(16, 16, (350.0, 2000.0), (-500.0, 500.0), (min(1.0, n / 4096.0 / 2),))
     dtype = np.float64 if prec == "f64" else np.float32
     tdt = torch.float64 if prec == "f64" else torch.float32
     cap = 1 << 18
-    with bfs.Plan(n, 4096.0, kappa=4.0, grid=grid, precision=prec, tail_capacity=cap, pairs=pairs) as plan:
+    with bfs.Plan(n, 4096.0, kappa=4.0, grid=grid, precision=prec, tail_capacity=cap, pairs=pairs,
+                  fused=form == "fused") as plan:
         tails_buf = torch.empty(cap * bfs.TAIL_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
         count = torch.empty(1, dtype=torch.int64, device="cuda:0")
         for call, S in enumerate(counts):
