@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # for the kernel sources and build flags they were taken on
 # (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "ebbc61df0cbc17ea": {"f32": 2.2065e+09, "f32-w16f": 1.0890e+09},
+    "108883633739917c": {"f32": 2.2073e+09, "f32-w16f": 1.0893e+09, "f32-w16b": 1.0890e+09, "f32 fused": 6.98e+06},
 }
 
 
@@ -120,6 +120,12 @@ def parse():
     p.add_argument("--serve-speed", type=float, default=50.0)
     p.add_argument("--slots", type=int, default=4)
     p.add_argument("--max-batch", type=int, default=8)
+    p.add_argument("--min-warmup-s", type=float, default=MIN_WARMUP_S,
+                   help="warm-up wall time each timed plan runs at least (clock settling)")
+    p.add_argument("--fused", action="store_true",
+                   help="the headline plan synthesises its templates per correlation (no resident bank)")
+    p.add_argument("--only-headline", action="store_true",
+                   help="time only the headline plan (and --no-fp16 aside, the 16-bit forms): for profilers")
     return p.parse_args()
 
 
@@ -452,7 +458,9 @@ def cpu_baseline(w, y, n_templates, min_seconds=10.0, max_passes=32):
 
 
 def main():
+    global MIN_WARMUP_S
     args = parse()
+    MIN_WARMUP_S = args.min_warmup_s
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: runs on one GPU only; multi-GPU runs are not supported "
               "(it would shard by templates or segments, one resident bank slice per GPU, with no "
@@ -477,14 +485,15 @@ def main():
     dense = {}  # precision form -> (workload, segment, GPU outputs) for the checker leg
     wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(
         bfs, torch, w, y_dev, args.precision, args.steps, args.warmup, args.depth,
-        collect=(0, w.n_templates) if check else None)
+        collect=(0, w.n_templates) if check else None, fused=args.fused)
     if check:
-        dense[f"{w.name} {args.precision}"] = (w, y, info.pop("dense"), args.precision)
+        dense[f"{w.name} {args.precision}{' fused' if args.fused else ''}"] = (w, y, info.pop("dense"), args.precision)
     k = w.n_templates
     value = args.steps * k / wall
     corr_avg_s = float(np.mean(corr_ms)) * 1e-3
     spec_bytes = SPEC_BYTES[args.precision]
-    r = roof(algorithmic_flops(w.n) * k, algorithmic_bytes(w.n, spec_bytes) * k, corr_avg_s)
+    flops_corr = fused_flops(w.n, w.taus[0] * w.fs) if args.fused else algorithmic_flops(w.n)
+    r = roof(flops_corr * k, 0.0 if args.fused else algorithmic_bytes(w.n, spec_bytes) * k, corr_avg_s)
     line = {
         "metric": "correlations/s (N=2^16, tau=1 s) on 1 MI355X",
         "value": value,
@@ -499,17 +508,18 @@ def main():
         "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.description}", "n": w.n, "templates": k, "segments": 1,
-                   "kappa": w.kappa, "precision": args.precision},
+                   "kappa": w.kappa, "precision": args.precision, "fused_synthesis": args.fused},
         "roofline": {
             "bound": "alu",
-            "kernel": "corr_kernel (fused product, sigma, inverse FFT, threshold, compaction)",
+            "kernel": ("corr_fused_kernel (synthesis, forward FFT, product, sigma, inverse FFT, threshold)"
+                       if args.fused else "corr_kernel (fused product, sigma, inverse FFT, threshold, compaction)"),
             "achieved": r["achieved_tflops"],
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",
             "frac": r["frac"],
-            "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(args.precision)
-            if w.name == "C2" else None,
-            "flops_per_correlation": algorithmic_flops(w.n),
+            "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get(
+                args.precision + (" fused" if args.fused else "")) if w.name == "C2" else None,
+            "flops_per_correlation": flops_corr,
             "correlations_per_launch": k,
             "kernel_ms_avg": corr_avg_s * 1e3,
             "hbm_algorithmic_GBps": r["hbm_achieved_GBps"],
@@ -550,7 +560,8 @@ def main():
         _ = float(a.sum())
         torch.cuda.synchronize()
         line["calibration_bytes"] = nbytes
-    if args.workload == "C2":
+    forms = args.workload == "C2" and not args.only_headline
+    if forms:
         # the paper's default output: per-lag max projection over templates (Sec. 3.3)
         wallp, _, corrp, _, n_peaks, _ = run_plan(bfs, torch, w, y_dev, args.precision, args.steps, args.warmup,
                                                  args.depth, project=True)
@@ -566,18 +577,19 @@ def main():
         line["band_threshold"] = {"kappa": 3.0, "kappa_hi": 3.5, "value": args.steps * k / wallb,
                                   "kernel_rate": k / (np.mean(corrb) * 1e-3), "tails_per_step": n_band}
         line["detector_pairs"] = run_pairs(bfs, torch, w, args)
-    if args.workload == "C2" and args.precision == "f32":
+    if forms and args.precision == "f32":
         # fused synthesis on the C2 workload: the same search with no resident bank
         wallf, buildf, corrf, _, _, infof = run_plan(bfs, torch, w, y_dev, "f32", args.steps, args.warmup,
                                                      args.depth, collect=(0, k) if check else None, fused=True)
         ksf = float(np.mean(corrf)) * 1e-3
         line["fused_synthesis"] = {"value": args.steps * k / wallf, "kernel_rate": k / ksf,
                                    "roofline": roof(fused_flops(w.n, w.taus[0] * w.fs) * k, 0.0, ksf),
+                                   "traffic": MEASURED_TRAFFIC.get(kernel_source_hash(), {}).get("f32 fused"),
                                    "ms_per_step": wallf / args.steps * 1e3, "plan_build_s": buildf,
                                    "bank_bytes": infof["bank_bytes"], "kernel": infof["kernel"]}
         if check:
             dense[f"{w.name} f32 fused"] = (w, y, infof.pop("dense"), "f32")
-    if not args.no_dense_bank and args.workload == "C2":
+    if not args.no_dense_bank and forms:
         for prec, key, fused in (("f32-w16f", "dense_bank_fp16", False), ("f32-w16b", "dense_bank_bf16", False),
                                  ("f32", "dense_bank_fp32_fused", True)):
             out, d3 = run_dense_bank(bfs, torch, 3, 1, precision=prec, collect=(0, 4096) if check else None,
@@ -586,9 +598,9 @@ def main():
             if check:
                 dense[f"C3 {prec}{' fused' if fused else ''}"] = (get_workload("C3"),
                                                                   make_segment(get_workload("C3"), 0)[0], d3, prec)
-    if not args.no_batched and args.workload == "C2":
+    if not args.no_batched and forms:
         line["batched"] = run_batched(bfs, torch, args.batched_steps, 1)
-    if not args.no_serving and args.workload == "C2":
+    if not args.no_serving and forms:
         line["serving"] = run_serving(bfs, torch, args)
     if not args.no_cpu_baseline:
         # checker leg: the oracle timed on the host cores, and every precision form's error

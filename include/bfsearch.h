@@ -105,15 +105,24 @@ typedef enum {
 typedef struct bfs_plan bfs_plan; /* opaque: resident template banks, tables */
 typedef struct bfs_job bfs_job;   /* opaque: one bfsearch_filter call */
 
-/* One tail record (24 bytes).  rho is the correlation value rho_sj[lag] of
- * the convention above (not divided by sigma). */
+/* One tail record (16 bytes).  rho is the correlation value rho_sj[lag] of
+ * the convention above (not divided by sigma), FP32: the FP32 path's own
+ * precision; FP64 plans round theirs (bfs_tail64 keeps it). */
+typedef struct {
+  uint32_t segment;
+  uint32_t template_id;
+  uint32_t lag;
+  float rho;
+} bfs_tail;
+
+/* The same with an FP64 rho (24 bytes): the record the FP64 path writes. */
 typedef struct {
   uint32_t segment;
   uint32_t template_id;
   uint32_t lag;
   uint32_t reserved;
   double rho;
-} bfs_tail;
+} bfs_tail64;
 
 /* One entry of the per-lag max projection (16 bytes): at lag `lag` of
  * segment `segment`, the template with the largest |rho| / sigma among those
@@ -273,9 +282,10 @@ bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* se
  *   y_dev: n_segments segments of seg_len samples (0 = the plan's largest
  *          length; an accepted length) packed back to back, float (double for
  *          BFS_FP64 plans), caller device memory.
- *   tails_dev: caller device memory for tail_capacity records of
- *          bfs_tail (unsorted, in the order the kernels reserve them);
- *          tails past tail_capacity are counted but not written.
+ *   tails_dev: caller device memory for tail_capacity records of the
+ *          plan's type: bfs_tail (16 bytes) for BFS_FP32* plans, bfs_tail64
+ *          (24 bytes) for BFS_FP64 plans; unsorted, in the order the kernels
+ *          reserve them; tails past tail_capacity are counted, not written.
  *   count_dev: caller device memory, one uint64_t: set to 0 on the stream,
  *          then to the exact number of tails found.
  *   sigma_dev: caller device memory [n_segments][K] doubles, or NULL.
@@ -304,6 +314,11 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* plan, const void* y_dev, uint32_t s
  *   written are an arbitrary subset. */
 bfs_status bfsearch_fetch_tails(bfs_job* job, bfs_tail* out_host, uint64_t capacity,
                                 uint64_t* n_written, uint64_t* n_total);
+
+/* As bfsearch_fetch_tails, into 24-byte records with an FP64 rho (exact for
+ * FP64 plans, the FP32 value widened for the others). */
+bfs_status bfsearch_fetch_tails64(bfs_job* job, bfs_tail64* out_host, uint64_t capacity,
+                                  uint64_t* n_written, uint64_t* n_total);
 
 /* BFS_PLAN_PROJECT plans: wait for the job and copy its per-lag max
  * projection to out_host, sorted by (segment, lag), one entry per lag that

@@ -34,9 +34,10 @@ PLAN_PAIRS = 16
 PLAN_FUSED = 32
 PRECISIONS = {"f64": FP64, "f32": FP32, "f32-w16f": FP32_W16F, "f32-w16b": FP32_W16B}
 
-TAIL_DTYPE = np.dtype(
+TAIL_DTYPE = np.dtype([("segment", "<u4"), ("template", "<u4"), ("lag", "<u4"), ("rho", "<f4")])  # bfs_tail
+TAIL64_DTYPE = np.dtype(
     [("segment", "<u4"), ("template", "<u4"), ("lag", "<u4"), ("reserved", "<u4"), ("rho", "<f8")]
-)
+)  # bfs_tail64
 PEAK_DTYPE = np.dtype([("segment", "<u4"), ("lag", "<u4"), ("template", "<u4"), ("snr", "<f4")])
 COINC_DTYPE = np.dtype([("pair", "<u4"), ("lag", "<u4"), ("template_a", "<u4"), ("template_b", "<u4"),
                         ("snr_a", "<f4"), ("snr_b", "<f4")])
@@ -115,6 +116,7 @@ def _load() -> ctypes.CDLL:
         "bfsearch_filter": [vp, vp, vp, vp, u32, vp, ctypes.POINTER(vp)],
         "bfsearch_filter_noalloc": [vp, vp, u32, u32, vp, u64, vp, vp, vp],
         "bfsearch_fetch_tails": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
+        "bfsearch_fetch_tails64": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_sigma": [vp, vp],
         "bfsearch_fetch_projection": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
         "bfsearch_fetch_coincidences": [vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64)],
@@ -219,6 +221,8 @@ class Plan:
                 d.flags |= PLAN_SYMMETRIC
         self.precision = precision
         self.sample_dtype = "float64" if precision == "f64" else "float32"
+        # the record the kernels write (filter_noalloc's tail buffer), and fetch_tails' default
+        self.tail_dtype = TAIL64_DTYPE if precision == "f64" else TAIL_DTYPE
         self.tail_capacity = int(tail_capacity)
         self.device = int(device)
         self._h = ctypes.c_void_p()
@@ -312,9 +316,10 @@ class Plan:
         """The hot path with no allocation and no host synchronisation (bfsearch_filter_noalloc):
         queued on `stream` (default: current), returns at once.  y: [S, n_s] segments of one
         accepted length; tails_out: caller device memory for the unsorted tail records (a uint8
-        tensor of capacity * TAIL_DTYPE.itemsize bytes); count_out: one int64 on the device, set to
+        tensor of capacity * tail_dtype.itemsize bytes); count_out: one int64 on the device, set to
         the exact tail count; sigma_out: [S, K] float64 on the device, or None.  Calls that overlap
-        on one device share its scratch area and race; calls on one stream are ordered."""
+        on one device share its scratch area and race; calls on one stream are ordered.  The
+        records are the plan's tail_dtype (bfs_tail64 for FP64 plans, else bfs_tail)."""
         import torch
 
         y = self._check_tensor(y)
@@ -326,7 +331,7 @@ class Plan:
                 raise TypeError(f"output buffers must be contiguous CUDA tensors of {dt}")
         if count_out.numel() < 1:
             raise ValueError("count_out needs one element")
-        cap = tails_out.numel() // TAIL_DTYPE.itemsize
+        cap = tails_out.numel() // self.tail_dtype.itemsize
         sp = None
         if sigma_out is not None:
             if (not isinstance(sigma_out, torch.Tensor) or not sigma_out.is_cuda or sigma_out.dtype != torch.float64
@@ -397,13 +402,15 @@ class Job:
         self.lengths = list(lengths)
         self.n_segments = len(self.lengths)
 
-    def fetch_tails(self, capacity: int | None = None, allow_overflow: bool = False):
-        """Tails sorted by (segment, template, lag) as a TAIL_DTYPE array, and the exact total."""
+    def fetch_tails(self, capacity: int | None = None, allow_overflow: bool = False, wide: bool | None = None):
+        """Tails sorted by (segment, template, lag), and the exact total: TAIL_DTYPE records (FP32
+        rho), or with wide TAIL64_DTYPE (FP64 rho); the default is the plan's own record."""
         cap = self.plan.tail_capacity if capacity is None else int(capacity)
-        out = np.empty(cap, dtype=TAIL_DTYPE)  # only the first n_written records are filled
+        wide = self.plan.tail_dtype is TAIL64_DTYPE if wide is None else bool(wide)
+        out = np.empty(cap, dtype=TAIL64_DTYPE if wide else TAIL_DTYPE)  # the first n_written are filled
         nw, nt = ctypes.c_uint64(), ctypes.c_uint64()
-        st = _lib.bfsearch_fetch_tails(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw),
-                                       ctypes.byref(nt))
+        fetch = _lib.bfsearch_fetch_tails64 if wide else _lib.bfsearch_fetch_tails
+        st = fetch(self._h, ctypes.c_void_p(out.ctypes.data), cap, ctypes.byref(nw), ctypes.byref(nt))
         if st == BFS_ERR_TAIL_OVERFLOW and allow_overflow:
             return out[: nw.value], nt.value
         _check(st, "bfsearch_fetch_tails")
@@ -477,13 +484,13 @@ class Job:
         self.release()
 
 
-def tails_from_device(tails_out, count: int) -> np.ndarray:
+def tails_from_device(tails_out, count: int, dtype=TAIL_DTYPE) -> np.ndarray:
     """Decode the first min(count, capacity) records of a filter_noalloc tail buffer (a uint8 tensor)
-    into a TAIL_DTYPE array, in device order."""
-    cap = tails_out.numel() // TAIL_DTYPE.itemsize
+    of the plan's tail_dtype into a numpy array, in device order."""
+    cap = tails_out.numel() // dtype.itemsize
     n = min(int(count), cap)
-    raw = tails_out[: n * TAIL_DTYPE.itemsize].cpu().numpy()
-    return raw.view(TAIL_DTYPE).copy()
+    raw = tails_out[: n * dtype.itemsize].cpu().numpy()
+    return raw.view(dtype).copy()
 
 
 def status_string(status: int) -> str:

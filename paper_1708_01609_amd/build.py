@@ -18,7 +18,8 @@ LIB = os.path.join(HERE, "libbfsearch.so")
 SOURCES = [os.path.join(CSRC, f) for f in ("bfsearch.hip", "bfs_tail_sort.hip", "bfs_ks_f32.hip", "bfs_ks_w16f.hip",
                                            "bfs_ks_w16b.hip", "bfs_ks_f64.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("bfs_device.h", "bfs_fft3.h", "bfs_kernels.h", "bfs_fused.h",
-                                           "bfs_kernelset.h", "bfs_runtime_kernels.h", "bfs_tail_sort.h")] + [
+                                           "bfs_kernelset.h", "bfs_records.h", "bfs_runtime_kernels.h",
+                                           "bfs_tail_sort.h")] + [
     os.path.join(ROOT, "include", "bfsearch.h")
 ]
 ARCH = "gfx950"

@@ -350,7 +350,7 @@ __global__ __launch_bounds__(F::NT) void corr_fused_kernel(
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2, const double* __restrict__ f0,
     const double* __restrict__ fdot, const uint32_t* __restrict__ len, const float* __restrict__ norm, double fs,
     int taper, int sym, uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
-    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   static_assert(fused_shape<F>(), "fused kernels need a cubic transform with one column per thread");

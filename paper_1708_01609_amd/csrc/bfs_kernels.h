@@ -21,13 +21,9 @@
 #pragma once
 
 #include "bfs_fft3.h"
+#include "bfs_records.h"
 
 namespace bfs {
-
-struct tail_rec {
-  uint32_t segment, template_id, lag, reserved;
-  double rho;
-};
 
 enum Source : int { SRC_SAMPLES = 0, SRC_CHIRP = 1, SRC_EXPLICIT = 2, SRC_CHIRP_SYM = 3 };
 
@@ -454,7 +450,7 @@ __device__ __forceinline__ void emit_dense(Z&& z, uint32_t n_off, double N, cons
 // rootS = sqrt(S) = N sigma, so |rho| / sigma = |z| / rootS.
 template <class F, typename T, class Z>
 __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_hi, bool any, uint32_t s, uint32_t j,
-                                           double N, tail_rec* __restrict__ tails,
+                                           double N, tail_rec_t<T>* __restrict__ tails,
                                            unsigned long long* __restrict__ counter, uint64_t cap,
                                            unsigned long long* __restrict__ prow, double rootS, int t) {
   const int lane = t & 63;
@@ -500,12 +496,11 @@ __device__ __forceinline__ void emit_tails(Z&& z, uint32_t n_off, T thr, T thr_h
                                          (val < T(0) ? 1ull : 0ull);
           atomicMax(prow + lag, key);
         } else if (idx < cap) {
-          tail_rec r;
+          tail_rec_t<T> r{};
           r.segment = s;
           r.template_id = j;
           r.lag = lag;
-          r.reserved = 0;
-          r.rho = double(val) / N;
+          r.rho = decltype(r.rho)(double(val) / N);
           tails[idx] = r;
         }
         ++idx;
@@ -562,7 +557,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
-    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int M = F::M;
@@ -617,7 +612,7 @@ __global__ __launch_bounds__(F::NT) void corr2_kernel(
     const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
-    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int H = F::M, M = 2 * H;
@@ -842,7 +837,7 @@ __device__ __forceinline__ void pair_pre(cx<T>* v, double& acc_a, double& acc_b,
 template <class F, int E, typename T>
 __device__ __forceinline__ void emit_pair_tails(const cx<T>* v, const T* thr, const T* thr_hi, bool any,
                                                 const uint32_t* seg, uint32_t j, double N,
-                                                tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter,
+                                                tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter,
                                                 uint64_t cap, unsigned long long* const* prow, const double* rootS,
                                                 int t) {
   const int lane = t & 63;
@@ -881,12 +876,11 @@ __device__ __forceinline__ void emit_pair_tails(const cx<T>* v, const T* thr, co
                                          (val < T(0) ? 1ull : 0ull);
           atomicMax(prow[h] + lag, key);
         } else if (idx < cap) {
-          tail_rec r;
+          tail_rec_t<T> r{};
           r.segment = seg[h];
           r.template_id = j;
           r.lag = lag;
-          r.reserved = 0;
-          r.rho = double(val) / N;
+          r.rho = decltype(r.rho)(double(val) / N);
           tails[idx] = r;
         }
         ++idx;
@@ -900,7 +894,7 @@ __device__ __forceinline__ void pair_body(T* lds, double* red, cx<T>* stash, con
                                           const rsrc_t& rB, const uint32_t* seg, const uint32_t* prow_row, uint32_t jg,
                                           const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1,
                                           const cx<T>* __restrict__ tw2, double kappa, double kappa_hi,
-                                          double* __restrict__ sigma_out, uint32_t k_total, tail_rec* __restrict__ tails,
+                                          double* __restrict__ sigma_out, uint32_t k_total, tail_rec_t<T>* __restrict__ tails,
                                           unsigned long long* __restrict__ counter, uint64_t cap,
                                           unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off,
                                           T* __restrict__ rho_dense, int t) {
@@ -960,7 +954,7 @@ __global__ __launch_bounds__(F::NT) void pair_kernel(
     const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
     const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
     uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
-    tail_rec* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int M = F::M;

@@ -50,7 +50,7 @@ struct CorrArgs {
   uint32_t tile;            // segments per tile of the workgroup order (1 <= tile <= rows)
   double kappa;
   double* sigma;
-  tail_rec* tails;
+  void* tails;              // tail records of the set's type (tail_rec_t of its real type)
   unsigned long long* counter;
   uint64_t cap;
   unsigned long long* proj;  // projection keys (null: tail list)
@@ -77,6 +77,7 @@ struct KernelSet {
   int G;             // load-group depth of the product stage
   size_t real_size;  // sizeof(T)
   size_t spec_size;  // bytes of one stored template spectrum element
+  size_t tail_size;  // bytes of one tail record the kernels write
   hipError_t (*fwd)(int src, uint32_t batch, hipStream_t st, const FwdArgs& a);
   hipError_t (*unpack_bank)(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
                             const void* tw_u, uint64_t row_off);
@@ -142,8 +143,9 @@ struct Impl {
       hipLaunchKernelGGL((corr_fused_kernel<T, F, DENSE, G, NZ>), dim3(blocks), dim3(F::NT), 0, st, y, seg_ids,
                          static_cast<const cx<T>*>(a.tw_u), static_cast<const cx<T>*>(a.tw1),
                          static_cast<const cx<T>*>(a.tw2), a.f0 + j0, a.fdot + j0, a.len + j0, a.norm + j0, a.fs,
-                         a.taper, a.sym, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
-                         a.kappa_hi, DENSE ? static_cast<T*>(a.rho) : nullptr, j0, a.K, row0);
+                         a.taper, a.sym, kn, rn, tile, a.kappa, a.sigma, static_cast<tail_rec_t<T>*>(a.tails),
+                         a.counter, a.cap, a.proj, proj_off, a.kappa_hi, DENSE ? static_cast<T*>(a.rho) : nullptr, j0,
+                         a.K, row0);
     }
   }
   template <bool DENSE, int MODE>
@@ -154,6 +156,7 @@ struct Impl {
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
     T* rho = DENSE ? static_cast<T*>(a.rho) : nullptr;
+    auto* tails = static_cast<tail_rec_t<T>*>(a.tails);
     constexpr bool PAIR = MODE == MODE_PAIR;
     if constexpr (MODE == MODE_FUSED) {
       if (a.rows <= uint32_t(FUSED_NZ))
@@ -162,15 +165,15 @@ struct Impl {
         launch_fused<DENSE, F::R1>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
     } else if constexpr (PAIR && !SPLIT)
       hipLaunchKernelGGL((pair_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
-                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
     else if constexpr (SPLIT)
       hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
-                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
     else
       hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
-                         t1, t2, kn, rn, tile, a.kappa, a.sigma, a.tails, a.counter, a.cap, a.proj, proj_off,
+                         t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
   }
   // 1-D grids in the XCD-aware order of tile_map, 8 ceil(K/8) S workgroups in all.  A
@@ -242,7 +245,7 @@ struct Impl {
     return hipGetLastError();
   }
   static const KernelSet* get() {
-    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW),
+    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW), sizeof(tail_rec_t<T>),
                                  &fwd, &unpack_bank, &unpack_y, &corr, SPLIT ? nullptr : &corr_pair, &export_bank,
                                  &export_y, FUSED ? &corr_fused : nullptr, FUSED ? &permute_y : nullptr,
                                  FUSED_NZ};

@@ -4,21 +4,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace bfs {
+#include "bfs_records.h"
 
-// Same layout as the kernels' tail record and the ABI's bfs_tail.
-struct tail_sort_rec {
-  uint32_t segment, template_id, lag, reserved;
-  double rho;
-};
+namespace bfs {
 
 // Device bytes of the work area for sorting n records (0 if n is 0 or above 2^31 - 1).
 size_t tail_sort_work_bytes(uint64_t n);
 
-// Queue on st: out[0..n) = tails[0..n) in (segment, template_id, lag) order.
+// Queue on st: out[0..n) = tails[0..n) in (segment, template_id, lag) order,
+// for records of rec_bytes bytes (sizeof(tail_rec) or sizeof(tail_rec64)).
 // end_bit: highest key bit + 1 that can be set (48 + the bits of the largest
 // segment index; 64 always works).  work: tail_sort_work_bytes(n) device bytes.
-hipError_t tail_sort(const tail_sort_rec* tails, uint64_t n, uint32_t end_bit, void* work, size_t work_bytes,
-                     tail_sort_rec* out, hipStream_t st);
+hipError_t tail_sort(const void* tails, size_t rec_bytes, uint64_t n, uint32_t end_bit, void* work,
+                     size_t work_bytes, void* out, hipStream_t st);
 
 }  // namespace bfs

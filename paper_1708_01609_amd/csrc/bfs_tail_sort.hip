@@ -15,18 +15,19 @@ namespace bfs {
 
 namespace {
 
-__global__ __launch_bounds__(256) void tail_keys_kernel(const tail_sort_rec* __restrict__ t, uint64_t n,
+template <typename R>
+__global__ __launch_bounds__(256) void tail_keys_kernel(const R* __restrict__ t, uint64_t n,
                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ idx) {
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const tail_sort_rec r = t[i];
+  const R r = t[i];
   keys[i] = (uint64_t(r.segment) << 48) | (uint64_t(r.template_id) << 17) | uint64_t(r.lag);
   idx[i] = uint32_t(i);
 }
 
-__global__ __launch_bounds__(256) void tail_gather_kernel(const tail_sort_rec* __restrict__ t,
-                                                          const uint32_t* __restrict__ idx, uint64_t n,
-                                                          tail_sort_rec* __restrict__ out) {
+template <typename R>
+__global__ __launch_bounds__(256) void tail_gather_kernel(const R* __restrict__ t, const uint32_t* __restrict__ idx,
+                                                          uint64_t n, R* __restrict__ out) {
   const uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < n) out[i] = t[idx[i]];
 }
@@ -51,8 +52,9 @@ size_t tail_sort_work_bytes(uint64_t n) {
   return 2 * align256(n * sizeof(uint64_t)) + 2 * align256(n * sizeof(uint32_t)) + align256(t);
 }
 
-hipError_t tail_sort(const tail_sort_rec* tails, uint64_t n, uint32_t end_bit, void* work, size_t work_bytes,
-                     tail_sort_rec* out, hipStream_t st) {
+template <typename R>
+hipError_t tail_sort_t(const R* tails, uint64_t n, uint32_t end_bit, void* work, size_t work_bytes, R* out,
+                       hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (n > 0x7fffffffull || end_bit < 17 || end_bit > 64 || work_bytes < tail_sort_work_bytes(n))
     return hipErrorInvalidValue;
@@ -67,13 +69,24 @@ hipError_t tail_sort(const tail_sort_rec* tails, uint64_t n, uint32_t end_bit, v
   w += align256(n * sizeof(uint32_t));
   size_t temp = cub_temp_bytes(n);
   const dim3 grid(uint32_t((n + 255) / 256));
-  hipLaunchKernelGGL(tail_keys_kernel, grid, dim3(256), 0, st, tails, n, k0, i0);
+  hipLaunchKernelGGL(tail_keys_kernel<R>, grid, dim3(256), 0, st, tails, n, k0, i0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = hipcub::DeviceRadixSort::SortPairs(static_cast<void*>(w), temp, k0, k1, i0, i1, int(n), 0, int(end_bit), st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(tail_gather_kernel, grid, dim3(256), 0, st, tails, i1, n, out);
+  hipLaunchKernelGGL(tail_gather_kernel<R>, grid, dim3(256), 0, st, tails, i1, n, out);
   return hipGetLastError();
+}
+
+hipError_t tail_sort(const void* tails, size_t rec_bytes, uint64_t n, uint32_t end_bit, void* work,
+                     size_t work_bytes, void* out, hipStream_t st) {
+  if (rec_bytes == sizeof(tail_rec))
+    return tail_sort_t(static_cast<const tail_rec*>(tails), n, end_bit, work, work_bytes, static_cast<tail_rec*>(out),
+                       st);
+  if (rec_bytes == sizeof(tail_rec64))
+    return tail_sort_t(static_cast<const tail_rec64*>(tails), n, end_bit, work, work_bytes,
+                       static_cast<tail_rec64*>(out), st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace bfs

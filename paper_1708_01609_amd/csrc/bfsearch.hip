@@ -22,7 +22,7 @@
 using namespace bfs;
 
 static_assert(sizeof(tail_rec) == sizeof(bfs_tail), "tail record layout");
-static_assert(sizeof(tail_sort_rec) == sizeof(bfs_tail), "tail record layout");
+static_assert(sizeof(tail_rec64) == sizeof(bfs_tail64), "tail record layout");
 static_assert(sizeof(coinc_rec) == sizeof(bfs_coinc), "coincidence record layout");
 
 namespace {
@@ -124,7 +124,7 @@ struct JobBuffers {
   void* y = nullptr;
   void* z = nullptr;
   double* sigma = nullptr;
-  tail_rec* tails = nullptr;
+  void* tails = nullptr;  // device tail records of the plan's type (tail_rec or tail_rec64)
   unsigned long long* counter = nullptr;
   void* meta = nullptr;       // device segment table
   void* meta_host = nullptr;  // pinned host staging of the table
@@ -132,7 +132,7 @@ struct JobBuffers {
   unsigned long long* plist = nullptr;       // compacted (index, key) pairs
   coinc_rec* clist = nullptr;                // coincidences of detector pairs
   unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
-  bfs_tail* tails_host = nullptr;            // pinned staging of fetched tails
+  void* tails_host = nullptr;                // pinned staging of fetched tails (the plan's records)
   uint64_t tails_host_cap = 0;
   void* sorted = nullptr;  // device: sorted tail records [sort_cap], then the sort's work area
   uint64_t sort_cap = 0;
@@ -175,6 +175,7 @@ struct bfs_plan {
   double kappa = 0.0, kappa_hi = 0.0;
   uint64_t cap = 0;
   std::vector<SizePlan> sizes;  // ascending N: sizes[i].N = n_min << i
+  size_t rec_bytes = sizeof(tail_rec);  // tail record the kernels write: 24 bytes for FP64, else 16
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
   bool graph = false;
   bool project = false;  // per-lag max projection instead of the tail list
@@ -376,7 +377,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const uint64_t ybytes = uint64_t(sp.M) * 2 * sp.ks->real_size;
   bfs_status st = alloc_checked(&y, ybytes);
-  if (st == BFS_OK) st = alloc_checked(&tails, sizeof(tail_rec));
+  if (st == BFS_OK) st = alloc_checked(&tails, sizeof(tail_rec64));
   if (st == BFS_OK) st = alloc_checked(&counter, 256);
   if (st == BFS_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) st = BFS_ERR_HIP;
   hipStream_t s = p->copy_stream;
@@ -394,7 +395,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
     a.tw2 = sp.tw2;
     a.K = Kt;
     a.kappa = p->kappa;
-    a.tails = static_cast<tail_rec*>(tails);
+    a.tails = tails;
     a.counter = static_cast<unsigned long long*>(counter);
     a.cap = 1;
     float ms_min = 0.f;
@@ -435,7 +436,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
     a.K = Kt;
     a.tile = TILES[i];
     a.kappa = p->kappa;
-    a.tails = static_cast<tail_rec*>(tails);
+    a.tails = tails;
     a.counter = static_cast<unsigned long long*>(counter);
     a.cap = 1;
     float ms_min = 0.f;
@@ -631,8 +632,8 @@ bool covers(const JobNeed& c, const JobNeed& n) {
          c.coinc >= n.coinc;
 }
 
-uint64_t need_bytes(const JobNeed& c, uint64_t cap) {
-  return c.ybytes + c.zbytes + c.sigma * sizeof(double) + cap * sizeof(tail_rec) + c.meta + 3 * 8 * c.proj +
+uint64_t need_bytes(const JobNeed& c, uint64_t cap, size_t rec_bytes) {
+  return c.ybytes + c.zbytes + c.sigma * sizeof(double) + cap * rec_bytes + c.meta + 3 * 8 * c.proj +
          c.coinc * sizeof(coinc_rec) + 256;
 }
 
@@ -657,10 +658,10 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
     c.proj = std::max(c.proj, b->cap.proj);
     c.coinc = std::max(c.coinc, b->cap.coinc);
   }
-  uint64_t bytes = need_bytes(c, p->cap);
+  uint64_t bytes = need_bytes(c, p->cap, p->rec_bytes);
   if (p->plan_bytes + p->live_job_bytes + bytes > p->budget) {
     c = need;  // the minimal set, after dropping the pool
-    bytes = need_bytes(c, p->cap);
+    bytes = need_bytes(c, p->cap, p->rec_bytes);
   }
   for (auto* b : p->pool) free_job_buffers(b);
   p->pool.clear();
@@ -673,7 +674,7 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
   bfs_status st = alloc_checked(&b->y, c.ybytes);
   if (st == BFS_OK && c.zbytes) st = alloc_checked(&b->z, c.zbytes);
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->sigma), c.sigma * sizeof(double));
-  if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->tails), p->cap * sizeof(tail_rec));
+  if (st == BFS_OK) st = alloc_checked(&b->tails, p->cap * p->rec_bytes);
   if (st == BFS_OK) st = alloc_checked(reinterpret_cast<void**>(&b->counter), 256);
   if (st == BFS_OK) st = alloc_checked(&b->meta, c.meta);
   if (st == BFS_OK && c.proj) st = alloc_checked(reinterpret_cast<void**>(&b->proj), c.proj * 8);
@@ -1026,7 +1027,7 @@ hipError_t read_counters(bfs_plan* p, JobBuffers* b) {
 // Fetches of at least DEVICE_SORT_MIN tails are ordered on the device.
 constexpr uint64_t DEVICE_SORT_MIN = 1u << 15;
 
-uint64_t sort_out_bytes(uint64_t n) { return (n * sizeof(bfs_tail) + 255) & ~uint64_t(255); }
+uint64_t sort_out_bytes(uint64_t n, size_t rec_bytes) { return (n * rec_bytes + 255) & ~uint64_t(255); }
 
 // Make b's device sort area hold n records (grown to at most the tail
 // capacity, kept with the buffers).  Its bytes count against the plan's HBM
@@ -1037,7 +1038,7 @@ bool ensure_sort(bfs_plan* p, JobBuffers* b, uint64_t n) {
   const uint64_t want = std::min<uint64_t>(p->cap, std::max<uint64_t>(n, 2 * b->sort_cap));
   const size_t work = tail_sort_work_bytes(want);
   if (!work) return false;
-  const uint64_t bytes = sort_out_bytes(want) + work;
+  const uint64_t bytes = sort_out_bytes(want, p->rec_bytes) + work;
   std::lock_guard<std::mutex> lk(p->mu);
   // the pooled buffer sets still hold device memory: count them, and give them back to the
   // device when the sort area fits only without them
@@ -1070,8 +1071,9 @@ bool ensure_sort(bfs_plan* p, JobBuffers* b, uint64_t n) {
 // deterministic.  LSD radix sort (16-bit digits) of the packed key
 // segment << 48 | template_id << 17 | lag when every field fits (segments
 // < 2^16, templates < 2^31, lags < 2^17), else a comparison sort.
-void sort_tails(bfs_tail* t, uint64_t n) {
-  auto less = [](const bfs_tail& a, const bfs_tail& c) {
+template <typename R>
+void sort_tails(R* t, uint64_t n) {
+  auto less = [](const R& a, const R& c) {
     if (a.segment != c.segment) return a.segment < c.segment;
     if (a.template_id != c.template_id) return a.template_id < c.template_id;
     return a.lag < c.lag;
@@ -1108,8 +1110,106 @@ void sort_tails(bfs_tail* t, uint64_t n) {
     key.swap(key2);
     idx.swap(idx2);
   }
-  std::vector<bfs_tail> tmp(t, t + n);
+  std::vector<R> tmp(t, t + n);
   for (uint64_t i = 0; i < n; ++i) t[i] = tmp[idx[i]];
+}
+
+// The job's tails, ordered by (segment, template_id, lag), in the plan's
+// record type in the job's pinned staging buffer: from 32,768 tails up
+// sorted on the device (when the sort area fits the budget), else on the
+// host.  *count: tails the kernels found; *on_dev: records the buffer holds.
+template <typename R>
+bfs_status sorted_tails(bfs_job* j, const R** recs, uint64_t* on_dev_out, unsigned long long* count_out) {
+  bfs_plan* p = j->plan;
+  JobBuffers* b = j->buf;
+  HIP_TRY(hipEventSynchronize(b->ev[b->done]));
+  HIP_TRY(read_counters(p, b));
+  const unsigned long long count = *b->count_host;
+  const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
+  if (on_dev > b->tails_host_cap) {
+    if (b->tails_host) (void)hipHostFree(b->tails_host);
+    b->tails_host = nullptr;
+    b->tails_host_cap = 0;
+    const uint64_t want = std::min<uint64_t>(p->cap, std::max<uint64_t>(on_dev, 2 * on_dev));
+    if (hipHostMalloc(&b->tails_host, want * sizeof(R), hipHostMallocDefault) != hipSuccess) {
+      b->tails_host = nullptr;
+      (void)hipGetLastError();
+      return BFS_ERR_OUT_OF_MEMORY;
+    }
+    b->tails_host_cap = want;
+  }
+  R* tmp = static_cast<R*>(b->tails_host);
+  bool sorted = false;
+  if (on_dev >= DEVICE_SORT_MIN && p->K < (1u << 31) && p->n_max <= (1u << 17) && ensure_sort(p, b, on_dev)) {
+    // order on the device, then one copy of the sorted records
+    const uint32_t end_bit = j->S > 1 ? 48u + uint32_t(32 - __builtin_clz(j->S - 1)) : 48u;
+    char* work = static_cast<char*>(b->sorted) + sort_out_bytes(b->sort_cap, sizeof(R));
+    if (tail_sort(b->tails, sizeof(R), on_dev, end_bit, work, b->sort_bytes - sort_out_bytes(b->sort_cap, sizeof(R)),
+                  b->sorted, p->copy_stream) == hipSuccess) {
+      HIP_TRY(hipMemcpyAsync(tmp, b->sorted, on_dev * sizeof(R), hipMemcpyDeviceToHost, p->copy_stream));
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+      sorted = true;
+    } else {
+      (void)hipGetLastError();
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+    }
+  }
+  if (!sorted) {
+    if (on_dev) {
+      HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(R), hipMemcpyDeviceToHost, p->copy_stream));
+      HIP_TRY(hipStreamSynchronize(p->copy_stream));
+    }
+    sort_tails(tmp, on_dev);
+  }
+  *recs = tmp;
+  *on_dev_out = on_dev;
+  *count_out = count;
+  return BFS_OK;
+}
+
+// One record of the plan's type as the caller's record type (the value of rho
+// rounded to float for bfs_tail, exact for bfs_tail64).
+template <typename Out, typename R>
+Out as_record(const R& r) {
+  Out o{};
+  o.segment = r.segment;
+  o.template_id = r.template_id;
+  o.lag = r.lag;
+  o.rho = decltype(o.rho)(r.rho);
+  return o;
+}
+
+template <typename Out>
+bfs_status fetch_tails_as(bfs_job* j, Out* out_host, uint64_t capacity, uint64_t* n_written, uint64_t* n_total) {
+  if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
+  bfs_plan* p = j->plan;
+  if (p->project) return BFS_ERR_INVALID_ARG;
+  if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
+  uint64_t on_dev = 0, nw = 0;
+  unsigned long long count = 0;
+  bfs_status st;
+  auto copy = [&](const auto* r) {
+    using R = std::remove_cv_t<std::remove_pointer_t<decltype(r)>>;
+    nw = std::min<uint64_t>(on_dev, capacity);
+    if (sizeof(R) == sizeof(Out)) {  // the caller's record is the plan's (same layout)
+      if (nw) std::memcpy(out_host, r, nw * sizeof(Out));
+    } else {
+      for (uint64_t i = 0; i < nw; ++i) out_host[i] = as_record<Out>(r[i]);
+    }
+  };
+  if (p->rec_bytes == sizeof(tail_rec64)) {
+    const tail_rec64* r = nullptr;
+    st = sorted_tails(j, &r, &on_dev, &count);
+    if (st == BFS_OK) copy(r);
+  } else {
+    const tail_rec* r = nullptr;
+    st = sorted_tails(j, &r, &on_dev, &count);
+    if (st == BFS_OK) copy(r);
+  }
+  if (st != BFS_OK) return st;
+  *n_written = nw;
+  *n_total = count;
+  return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
 }
 
 // ------------------------------------------------------------ no-allocation scratch --
@@ -1177,6 +1277,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
   p->kappa = d->kappa;
   p->kappa_hi = d->kappa_hi;
   p->cap = d->tail_capacity;
+  p->rec_bytes = d->precision == BFS_FP64 ? sizeof(tail_rec64) : sizeof(tail_rec);
   size_plans(p, d, (d->flags & BFS_PLAN_FUSED) != 0);
   p->pairs = (d->flags & BFS_PLAN_PAIRS) != 0;
   p->delta = d->coinc_delta_hz;
@@ -1362,7 +1463,7 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   c.kappa = p->kappa;
   c.kappa_hi = p->kappa_hi;
   c.sigma = sigma_dev;
-  c.tails = static_cast<tail_rec*>(tails_dev);
+  c.tails = tails_dev;
   c.counter = counter;
   c.cap = tail_capacity;
   if (p->fused) {
@@ -1376,57 +1477,12 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
 
 bfs_status bfsearch_fetch_tails(bfs_job* j, bfs_tail* out_host, uint64_t capacity, uint64_t* n_written,
                                 uint64_t* n_total) {
-  if (!j || !n_written || !n_total || (capacity > 0 && !out_host)) return BFS_ERR_INVALID_ARG;
-  bfs_plan* p = j->plan;
-  if (p->project) return BFS_ERR_INVALID_ARG;
-  JobBuffers* b = j->buf;
-  if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
-  HIP_TRY(hipEventSynchronize(b->ev[b->done]));
-  HIP_TRY(read_counters(p, b));
-  const unsigned long long count = *b->count_host;
-  const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
-  if (on_dev > b->tails_host_cap) {
-    if (b->tails_host) (void)hipHostFree(b->tails_host);
-    b->tails_host = nullptr;
-    b->tails_host_cap = 0;
-    const uint64_t want = std::min<uint64_t>(p->cap, std::max<uint64_t>(on_dev, 2 * on_dev));
-    if (hipHostMalloc(reinterpret_cast<void**>(&b->tails_host), want * sizeof(bfs_tail), hipHostMallocDefault) !=
-        hipSuccess) {
-      b->tails_host = nullptr;
-      (void)hipGetLastError();
-      return BFS_ERR_OUT_OF_MEMORY;
-    }
-    b->tails_host_cap = want;
-  }
-  bfs_tail* tmp = b->tails_host;
-  bool sorted = false;
-  if (on_dev >= DEVICE_SORT_MIN && p->K < (1u << 31) && p->n_max <= (1u << 17) && ensure_sort(p, b, on_dev)) {
-    // order on the device, then one copy of the sorted records
-    const uint32_t end_bit = j->S > 1 ? 48u + uint32_t(32 - __builtin_clz(j->S - 1)) : 48u;
-    auto* out = static_cast<tail_sort_rec*>(b->sorted);
-    char* work = static_cast<char*>(b->sorted) + sort_out_bytes(b->sort_cap);
-    if (tail_sort(reinterpret_cast<const tail_sort_rec*>(b->tails), on_dev, end_bit, work,
-                  b->sort_bytes - sort_out_bytes(b->sort_cap), out, p->copy_stream) == hipSuccess) {
-      HIP_TRY(hipMemcpyAsync(tmp, out, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
-      HIP_TRY(hipStreamSynchronize(p->copy_stream));
-      sorted = true;
-    } else {
-      (void)hipGetLastError();
-      HIP_TRY(hipStreamSynchronize(p->copy_stream));
-    }
-  }
-  if (!sorted) {
-    if (on_dev) {
-      HIP_TRY(hipMemcpyAsync(tmp, b->tails, on_dev * sizeof(bfs_tail), hipMemcpyDeviceToHost, p->copy_stream));
-      HIP_TRY(hipStreamSynchronize(p->copy_stream));
-    }
-    sort_tails(tmp, on_dev);
-  }
-  const uint64_t nw = std::min<uint64_t>(on_dev, capacity);
-  if (nw) std::memcpy(out_host, tmp, nw * sizeof(bfs_tail));
-  *n_written = nw;
-  *n_total = count;
-  return (count > nw) ? BFS_ERR_TAIL_OVERFLOW : BFS_OK;
+  return fetch_tails_as(j, out_host, capacity, n_written, n_total);
+}
+
+bfs_status bfsearch_fetch_tails64(bfs_job* j, bfs_tail64* out_host, uint64_t capacity, uint64_t* n_written,
+                                  uint64_t* n_total) {
+  return fetch_tails_as(j, out_host, capacity, n_written, n_total);
 }
 
 bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t capacity, uint64_t* n_written,
@@ -1538,7 +1594,7 @@ bfs_status bfsearch_plan_job_bytes(const bfs_plan* p, const uint32_t* seg_length
   Layout L;
   const bfs_status rs = make_layout(p, seg_lengths, S, L);
   if (rs != BFS_OK) return rs;
-  *bytes = need_bytes(L.need, p->cap);
+  *bytes = need_bytes(L.need, p->cap, p->rec_bytes);
   return BFS_OK;
 }
 

@@ -46,7 +46,7 @@ def test_library_exports_every_declared_symbol(bfs):
 
 def test_struct_layouts_match_header(bfs):
     assert ctypes.sizeof(bfs.PlanInfo) == 48
-    assert bfs.TAIL_DTYPE.itemsize == 24
+    assert bfs.TAIL_DTYPE.itemsize == 16 and bfs.TAIL64_DTYPE.itemsize == 24
     assert bfs.PEAK_DTYPE.itemsize == 16
     assert bfs.COINC_DTYPE.itemsize == 24
     # bfs_plan_desc field order as declared (spot-check offsets of the 64-bit fields)

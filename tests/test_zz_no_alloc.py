@@ -52,7 +52,7 @@ def test_noalloc_matches_filter(bfs, prec, n, form, counts):
     cap = 1 << 18
     with bfs.Plan(n, 4096.0, kappa=4.0, grid=grid, precision=prec, tail_capacity=cap, pairs=pairs,
                   fused=form == "fused") as plan:
-        tails_buf = torch.empty(cap * bfs.TAIL_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+        tails_buf = torch.empty(cap * plan.tail_dtype.itemsize, dtype=torch.uint8, device="cuda:0")
         count = torch.empty(1, dtype=torch.int64, device="cuda:0")
         for call, S in enumerate(counts):
             y = _segments(n, S, dtype, seed=1000 * call + n + (7 if pairs else 0))
@@ -62,7 +62,7 @@ def test_noalloc_matches_filter(bfs, prec, n, form, counts):
             plan.filter_noalloc(y_dev, tails_buf, count, sigma)
             torch.cuda.synchronize()
             total = int(count.item())
-            got = bfs.tails_from_device(tails_buf, total)
+            got = bfs.tails_from_device(tails_buf, total, plan.tail_dtype)
             got = got[_key(got)]
             with plan.filter(y_dev) as job:
                 want, want_total = job.fetch_tails()
@@ -81,7 +81,7 @@ def test_noalloc_rejects_what_does_not_fit(bfs):
     with bfs.Plan(n, 4096.0, kappa=5.0, grid=grid, precision="f32") as plan:
         s_max = bfs.NOALLOC_SCRATCH_BYTES // (n * 4)  # FP32 spectra: 4 bytes per sample
         y = torch.zeros((s_max + 1, n), dtype=torch.float32, device="cuda:0")
-        tails_buf = torch.empty(16 * bfs.TAIL_DTYPE.itemsize, dtype=torch.uint8, device="cuda:0")
+        tails_buf = torch.empty(16 * plan.tail_dtype.itemsize, dtype=torch.uint8, device="cuda:0")
         count = torch.zeros(1, dtype=torch.int64, device="cuda:0")
         with pytest.raises(bfs.BfsError) as e:
             plan.filter_noalloc(y, tails_buf, count)
