@@ -122,6 +122,8 @@ def parse():
     p.add_argument("--max-batch", type=int, default=8)
     p.add_argument("--min-warmup-s", type=float, default=MIN_WARMUP_S,
                    help="warm-up wall time each timed plan runs at least (clock settling)")
+    p.add_argument("--candidate", type=int, default=0,
+                   help="force kernel candidate i > 0 of each length for the headline plan (0: autotuned)")
     p.add_argument("--fused", action="store_true",
                    help="the headline plan synthesises its templates per correlation (no resident bank)")
     p.add_argument("--only-headline", action="store_true",
@@ -130,7 +132,7 @@ def parse():
 
 
 def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=False, symmetric=False, kappa=None,
-             kappa_hi=0.0, collect=None, pairs=False, fused=False):
+             kappa_hi=0.0, collect=None, pairs=False, fused=False, candidate=0):
     """Plan the workload, then time `steps` steps.  A step is one filter call (segment FFT +
     fused kernel over every template) and the fetch of its sorted tails; up to `depth` steps are
     queued on the stream, so the next step's kernels run while the host fetches and sorts the
@@ -146,8 +148,8 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=Fa
     grid = bfs.Grid(w.n_f0, w.n_fdot, w.f0_range, w.fdot_range, w.taus, symmetric=symmetric)
     t0 = time.perf_counter()
     plan = bfs.Plan(w.n, w.fs, kappa=w.kappa if kappa is None else kappa, grid=grid, precision=precision,
-                    tail_capacity=1 << 22, autotune=True, project=project, kappa_hi=kappa_hi, pairs=pairs,
-                    fused=fused)
+                    tail_capacity=1 << 22, autotune=not candidate, project=project, kappa_hi=kappa_hi, pairs=pairs,
+                    fused=fused, candidate=candidate)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     kernel = plan.kernel_info()
@@ -485,7 +487,7 @@ def main():
     dense = {}  # precision form -> (workload, segment, GPU outputs) for the checker leg
     wall, build_s, corr_ms, lat_ms, n_tails, info = run_plan(
         bfs, torch, w, y_dev, args.precision, args.steps, args.warmup, args.depth,
-        collect=(0, w.n_templates) if check else None, fused=args.fused)
+        collect=(0, w.n_templates) if check else None, fused=args.fused, candidate=args.candidate)
     if check:
         dense[f"{w.name} {args.precision}{' fused' if args.fused else ''}"] = (w, y, info.pop("dense"), args.precision)
     k = w.n_templates

@@ -232,6 +232,8 @@ typedef struct {
   uint32_t fused;               /* 1: templates synthesised per correlation (no bank) */
   uint32_t fused_rows;          /* fused: nonzero input rows of the forward
                                    transform's first pass */
+  uint32_t loop;                /* 1: as many workgroups as the device holds at
+                                   once, each looping over correlations */
 } bfs_kernel_info;
 
 /* Build a plan: synthesises every template on the device (FP64 phase and
@@ -290,7 +292,8 @@ bfs_status bfsearch_filter(bfs_plan* plan, const void* y_dev, const uint64_t* se
  *          then to the exact number of tails found.
  *   sigma_dev: caller device memory [n_segments][K] doubles, or NULL.
  * The spectra need n_segments * seg_len * 4 bytes (FP32; FP64: 8), twice that
- * at the lengths the library splits (2^17 FP32, 2^14 FP64); more than the
+ * for lengths of 2^12 samples and more and for fused plans (a scratch of the
+ * same size for the segment transform or the fused layout); more than the
  * scratch area is BFS_ERR_SCRATCH_LIMIT, before anything is queued.
  * BFS_ERR_INVALID_ARG for projection plans, an odd count on pair plans, or
  * a length the plan does not hold.  Every call on one device shares its

@@ -89,6 +89,7 @@ class KernelInfo(ctypes.Structure):
         ("tile_us", ctypes.c_float * 5),
         ("fused", ctypes.c_uint32),
         ("fused_rows", ctypes.c_uint32),
+        ("loop", ctypes.c_uint32),
     ]
 
 
@@ -242,7 +243,7 @@ class Plan:
                 "split": bool(ki.split), "candidate": ki.candidate, "n_candidates": ki.n_candidates,
                 "tuned_us": [float(ki.tuned_us[i]) for i in range(ki.n_candidates)],
                 "tile": ki.tile, "tile_us": {t: float(ki.tile_us[i]) for i, t in enumerate((1, 2, 4, 8, 16))},
-                "fused": bool(ki.fused), "fused_rows": ki.fused_rows}
+                "fused": bool(ki.fused), "fused_rows": ki.fused_rows, "loop": bool(ki.loop)}
 
     def held_bytes(self) -> int:
         """Device bytes the plan holds now (plan memory, live jobs, pooled buffer sets)."""

@@ -263,6 +263,42 @@ __device__ __forceinline__ void halfswap2(uint32_t a, uint32_t b, uint32_t& sa, 
   sa = r2[0];
   sb = r2[1];
 }
+// Per-lane blend: the lanes set in the constant mask take b, the others a.
+// One v_cndmask per register with the mask in an SGPR pair (written in asm:
+// the compiler turns such selects on single lanes into exec-masked branches).
+__device__ __forceinline__ uint32_t lane_sel(uint64_t mask, uint32_t a, uint32_t b) {
+  uint32_t r;
+  asm volatile("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+  return r;
+}
+template <typename T>
+__device__ __forceinline__ cx<T> lane_sel(uint64_t mask, const cx<T>& a, const cx<T>& b) {
+  constexpr int W = sizeof(cx<T>) / 4;
+  using V = typename std::conditional<W == 2, u32x2, u32x4>::type;
+  const V ua = __builtin_bit_cast(V, a), ub = __builtin_bit_cast(V, b);
+  V r;
+#pragma unroll
+  for (int i = 0; i < W; ++i) r[i] = lane_sel(mask, ua[i], ub[i]);
+  return __builtin_bit_cast(cx<T>, r);
+}
+
+// a as held by lane l ^ 32 (complex, any real type; one swap per register)
+template <typename T>
+__device__ __forceinline__ cx<T> halfrot(const cx<T>& a) {
+  constexpr int W = sizeof(cx<T>) / 4;
+  using V = typename std::conditional<W == 2, u32x2, u32x4>::type;
+  const V u = __builtin_bit_cast(V, a);
+  V s;
+#pragma unroll
+  for (int i = 0; i < W; i += 2) {
+    uint32_t x, y;
+    halfswap2(u[i], u[i + 1], x, y);
+    s[i] = x;
+    s[i + 1] = y;
+  }
+  return __builtin_bit_cast(cx<T>, s);
+}
+
 // pa = b and pb = a as held by lane l ^ 32 (complex, any real type)
 template <typename T>
 __device__ __forceinline__ void partner_pair(const cx<T>& a, const cx<T>& b, cx<T>& pa, cx<T>& pb) {

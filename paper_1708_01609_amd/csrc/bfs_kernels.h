@@ -42,7 +42,10 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
 
 // One forward transform per workgroup.  Segment items read their samples at
 // the device address seg_ptr[item], or at src + item src_stride (elements of
-// T) when seg_ptr is null; explicit templates at src + item src_stride.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
+// T) when seg_ptr is null; explicit templates at src + item src_stride.  With
+// zs > 1 (segments only) a segment's length-(zs F::M) transform is split zs
+// ways: workgroup b transforms the sub-sequence z_{r + zs m}, m < F::M, of
+// segment b / zs (r = b mod zs), for fft_join_kernel to combine.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
 // samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
 // The chirp source writes the FP64 sum of x^2 over the samples it made to
 // energy[b] (the unpack turns it into the unit-norm scale); SRC_CHIRP_SYM
@@ -53,14 +56,14 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     const double* __restrict__ f0, const double* __restrict__ fdot, const uint32_t* __restrict__ len,
     double fs, int taper, uint32_t first,
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    cx<T>* __restrict__ out, double* __restrict__ energy, int split) {
+    cx<T>* __restrict__ out, double* __restrict__ energy, int split, uint32_t zs) {
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
   const uint32_t b = blockIdx.x;
-  const uint32_t item = split ? (b >> 1) : b;
-  const uint32_t half = split ? (b & 1u) : 0u;
-  const uint32_t cs = split ? 2u : 1u;  // stride of z between the transform's samples
+  const uint32_t item = split ? (b >> 1) : (zs > 1 ? b / zs : b);
+  const uint32_t half = split ? (b & 1u) : (zs > 1 ? b % zs : 0u);
+  const uint32_t cs = split ? 2u : (zs > 1 ? zs : 1u);  // stride of z between the transform's samples
   cx<T> v[F::P];
   double acc = 0.0;
   uint32_t cols[F::C1];
@@ -212,6 +215,33 @@ __global__ __launch_bounds__(256) void rfft_unpack_kernel(const cx<T>* Z, TW* ou
   }
 }
 
+// Join of a transform split A ways by fwd_fft_kernel (zs = A): with the
+// sub-transforms T_r[k2] = sum_m z_{r + A m} exp(-2 pi i m k2 / B), B = M / A,
+//   Z_{k2 + B k1} = sum_{r<A} (T_r[k2] exp(-2 pi i r k2 / M)) exp(-2 pi i r k1 / A).
+// One thread per k2 of one segment (blockIdx.y): A loads, the twiddles from
+// tw_u (exp(+2 pi i k / N), k < M: exp(-2 pi i m / M) is conj(tw_u[2m]) or,
+// past M, -conj(tw_u[2m - M])), a length-A DFT, A stores; in and out are
+// [segments][M] (in: A rows of B).
+template <typename T, int A>
+__global__ __launch_bounds__(256) void fft_join_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
+                                                       const cx<T>* __restrict__ tw_u, uint32_t M) {
+  const uint32_t B = M / A;
+  const uint32_t k2 = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k2 >= B) return;
+  const uint64_t base = uint64_t(blockIdx.y) * M;
+  cx<T> v[A];
+#pragma unroll
+  for (int r = 0; r < A; ++r) {
+    const cx<T> a = in[base + uint64_t(r) * B + k2];
+    const uint32_t e = uint32_t((2ull * r * k2) % (2ull * M));  // 2 m mod N, m = r k2 mod M
+    const cx<T> w = e < M ? conjg(tw_u[e]) : cx<T>{-tw_u[e - M].x, tw_u[e - M].y};
+    v[r] = cmul(a, w);
+  }
+  dft<A, -1, T>(v);
+#pragma unroll
+  for (int k1 = 0; k1 < A; ++k1) out[base + k2 + uint64_t(B) * k1] = v[k1];
+}
+
 // Packed storage -> FP64 interleaved [rows][M+1][2] in natural bin order (diagnostics).
 template <typename T, typename TW>
 __global__ __launch_bounds__(256) void spectrum_export_kernel(const TW* __restrict__ in, double* __restrict__ out,
@@ -257,53 +287,99 @@ struct NoHook {
   __device__ void operator()(int, int) const {}
 };
 
-// The Hermitian repack of the product stage, in place on the registers of
-// every column c (twiddle get_bu(c) = exp(2 pi i k / N) of the column's first
-// bin, called once per column before its registers are repacked):
-//   Z_k = (C_k + conj C_{M-k}) + i exp(2 pi i k / N) (C_k - conj C_{M-k}).
-// cM: C_M (real) of column 0 under MAP_MIRROR.
-template <class F, int MAP, typename T, class BU>
-__device__ __forceinline__ void repack_mirror(cx<T>* v, T cM, int t, BU&& get_bu) {
-  constexpr bool HAS_DC = MAP == MAP_MIRROR;
-  const int lane = t & 63;
-  // wave-uniform (readfirstlane), so the other waves branch around the fixups
-  // instead of issuing them with an empty exec mask
-  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
+// Every Hermitian pair (k, M - k) of a block whose column c and partner column
+// S1 - c sit in lanes l and l ^ 32 of one wave (element (col, k2) pairs with
+// lane l ^ 32's register R1-1-k2), in place.  pair(c, r1, A, Bp, a, b) forms
+// from A (this lane's register r1 of column c) and Bp (its partner, register
+// r2 = R1-1-r1 of lane l ^ 32) the new value a of A and b of Bp: lane l takes
+// the pair (its own r1, lane l ^ 32's r2), fetches that register with a half
+// swap and returns b with another; the pairs of lane l ^ 32 are the mirror
+// image, so every pair is formed once.  col(c) runs before column c's pairs.
+// FIX: columns 0 and S1/2 (lanes 0 and 32 of wave 0, column slot 0) pair
+// inside their own lane: column S1/2 register r1 with r2, column 0 register r
+// with R1 - r, register 0 with `last` (whose result is dropped) and register
+// R1/2 with itself, whose new value is mid(its old value).  Wave 0 alone, in a
+// uniform branch, first gives lane 0 lane 32's registers R1/2..R1-1 and lane 32
+// lane 0's registers R1/2+1..R1-1 and `last`, so the common half swaps deliver
+// each lane its own partners, and afterwards moves the results back.
+template <class F, bool FIX, typename T, class Col, class Pair, class Mid>
+__device__ __forceinline__ void mirror_pairs(cx<T>* v, int t, const cx<T>& last, Col&& col, Pair&& pair,
+                                             Mid&& mid) {
+  constexpr int H = F::R1 / 2;
+  // wave-uniform (readfirstlane): the other waves branch around the fixups
+  const bool wave0 = FIX && __builtin_amdgcn_readfirstlane(t) < 64;
+  constexpr uint64_t L0 = 1ull, L32 = 1ull << 32;  // lane masks
+  cx<T> vmid = {T(0), T(0)};  // register R1/2 as it came (lane 0's is used)
+  if (wave0) {
+    vmid = v[H];
+    static_for<H>([&](auto kc) {
+      constexpr int r2 = H + decltype(kc)::value;  // ascending: v[r2 + 1] still unchanged
+      const cx<T> hr = halfrot(v[r2]);
+      cx<T> hn;
+      if constexpr (r2 + 1 < F::R1) {
+        hn = halfrot(v[r2 + 1]);
+      } else {
+        hn = halfrot(last);
+      }
+      v[r2] = lane_sel(L32, lane_sel(L0, v[r2], hr), hn);
+    });
+  }
 #pragma unroll
   for (int c = 0; c < F::C1; ++c) {
-    const cx<T> buc = get_bu(c);
-    cx<T> carry = {T(0), T(0)};
-    static_for<F::R1 / 2>([&](auto kc) {
+    col(c);
+    static_for<H>([&](auto kc) {
       constexpr int r1 = decltype(kc)::value;
       constexpr int r2 = F::R1 - 1 - r1;
-      const cx<T> A = v[c * F::R1 + r1], B = v[c * F::R1 + r2];
-      cx<T> PA, PB;
-      partner_pair(A, B, PA, PB);
-      if constexpr (HAS_DC) {
-        if (c == 0 && wave0) {
-          const cx<T> a0 = (r1 == 0) ? cx<T>{cM, T(0)} : carry;
-          const cx<T> b0 = (r1 + 1 == r2) ? B : v[c * F::R1 + r1 + 1];
-          PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
-          PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
-          PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
-          PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
-          carry = B;
-        }
-      }
-      auto repack = [&](const cx<T>& ck, const cx<T>& cp, const cx<T>& tk) {
-        const cx<T> a = {ck.x + cp.x, ck.y - cp.y};   // C_k + conj C_{M-k}
-        const cx<T> bq = {ck.x - cp.x, ck.y + cp.y};  // C_k - conj C_{M-k}
-        const cx<T> u = cmul(tk, bq);
-        return cx<T>{a.x - u.y, a.y + u.x};
-      };
-      v[c * F::R1 + r1] = repack(A, PA, rot<r1, 2 * F::R1, +1>(buc));
-      v[c * F::R1 + r2] = repack(B, PB, rot<r2, 2 * F::R1, +1>(buc));
+      cx<T> a, b;
+      pair(c, kc, v[c * F::R1 + r1], halfrot(v[c * F::R1 + r2]), a, b);
+      v[c * F::R1 + r1] = a;
+      v[c * F::R1 + r2] = halfrot(b);
       pin(v[c * F::R1 + r1]);
       pin(v[c * F::R1 + r2]);
       if constexpr (r1 % 4 == 3) sched_fence();
     });
     sched_fence();
   }
+  if (wave0) {
+    // lane 0 now holds lane 32's results in R1/2..R1-1, lane 32 lane 0's
+    // results of R1/2+1..R1-1 in R1/2..R1-2
+    static_for<H>([&](auto kc) {
+      constexpr int r2 = F::R1 - 1 - decltype(kc)::value;  // descending: v[r2 - 1] still unchanged
+      const cx<T> h = halfrot(v[r2]);
+      cx<T> l0;
+      if constexpr (r2 == H) {
+        l0 = mid(vmid);
+      } else {
+        l0 = halfrot(v[r2 - 1]);
+      }
+      v[r2] = lane_sel(L0, lane_sel(L32, v[r2], h), l0);
+    });
+  }
+}
+
+// The Hermitian repack of the product stage, in place on the registers of
+// every column c (twiddle get_bu(c) = exp(2 pi i k / N) of the column's first
+// bin, called once per column before its registers are repacked):
+//   Z_k = (C_k + conj C_{M-k}) + i t_k (C_k - conj C_{M-k}),  t_k = exp(2 pi i k / N).
+// With P = C_k + conj C_{M-k}, u = t_k (C_k - conj C_{M-k}) and
+// t_{M-k} = -conj t_k, the partner's value is Z_{M-k} = conj(P - i u): one
+// lane forms both from one twiddle (mirror_pairs).  Under MAP_MIRROR column 0
+// pairs register 0 with C_M (cM, real) and its register R1/2 (bin M/2) with
+// itself: Z = 2 conj C.
+template <class F, int MAP, typename T, class BU>
+__device__ __forceinline__ void repack_mirror(cx<T>* v, T cM, int t, BU&& get_bu) {
+  cx<T> buc;
+  mirror_pairs<F, MAP == MAP_MIRROR, T>(
+      v, t, cx<T>{cM, T(0)}, [&](int c) { buc = get_bu(c); },
+      [&](int, auto r1c, const cx<T>& A, const cx<T>& bp, cx<T>& za, cx<T>& zb) {
+        constexpr int r1 = decltype(r1c)::value;
+        const cx<T> tk = rot<r1, 2 * F::R1, +1>(buc);
+        const cx<T> P = {A.x + bp.x, A.y - bp.y};
+        const cx<T> u = cmul(tk, cx<T>{A.x - bp.x, A.y + bp.y});
+        za = cx<T>{P.x - u.y, P.y + u.x};
+        zb = cx<T>{P.x + u.y, u.x - P.y};  // Z_{M-k}
+      },
+      [&](const cx<T>& m) { return cx<T>{T(2) * m.x, T(-2) * m.y}; });
 }
 
 template <class F, int MAP, int G, typename T, typename TW, bool EARLY_BU = false, class Hook = NoHook>
@@ -322,6 +398,7 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
   constexpr uint32_t SW = sizeof(TW), SY = sizeof(cx<T>);
   constexpr bool HAS_DC = MAP == MAP_MIRROR;
   T cM = T(0);  // C_M of thread 0 (real)
+  double ha = 0.0, hb = 0.0;  // sum of |C_k|^2 / 2 over this thread's bins
   cx<T> bu[F::C1];  // the repack twiddle of each column
   if constexpr (EARLY_BU) {
 #pragma unroll
@@ -356,19 +433,29 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
           yk.y = dc ? T(0) : yk.y;
         }
         const cx<T> ck = cmulc(wk, yk);
-        double pk = 2.0 * (double(ck.x) * double(ck.x) + double(ck.y) * double(ck.y));
+        // |C_k|^2 into two FP64 chains (products of FP32 values are exact in
+        // FP64); the factor 2 is applied once at the end, so slot 0 of column
+        // 0 adds half of |C_0|^2 + |C_M|^2
+        const double dx = double(ck.x);
         if constexpr (HAS_DC && k2 == 0) {
-          const double pdc = double(ck.x) * double(ck.x) + double(cM) * double(cM);
-          pk = dc ? pdc : pk;
+          const double sc = dc ? 0.5 : 1.0;
+          const double dy = dc ? double(cM) : double(ck.y);
+          ha = fma(sc * dx, dx, ha);
+          hb = fma(sc * dy, dy, hb);
+        } else {
+          const double dy = double(ck.y);
+          ha = fma(dx, dx, ha);
+          hb = fma(dy, dy, hb);
         }
-        acc += pk;
         v[c * F::R1 + k2] = ck;
         pin(v[c * F::R1 + k2]);
       });
-      pin(acc);
+      pin(ha);
+      pin(hb);
       sched_fence();
     });
   }
+  acc += 2.0 * (ha + hb);
 
   repack_mirror<F, MAP, T>(v, cM, t, [&](int c) {
     if constexpr (!EARLY_BU) bu[c] = tw_u[bu_mul * cols[c] + bu_add];
@@ -379,7 +466,10 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
 // Stage 2: inverse transform of length F::M on chip.  Returns the workgroup
 // sum of every thread's acc, reduced in a fixed order (deterministic); with
 // NACC = 2 also the sum of acc2 into *S2 (red then holds 2 F::NW doubles).
-template <class F, typename T, int NACC = 1>
+// PRE_BARRIER: a workgroup barrier before the first LDS write of the
+// exchange, for callers that loop over correlations (every wave has then
+// left the previous correlation's exchanges, whatever it did before).
+template <class F, typename T, int NACC = 1, bool PRE_BARRIER = false>
 __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const uint32_t* cols,
                                             const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2, int t,
                                             double acc, double acc2 = 0.0, double* S2 = nullptr) {
@@ -393,6 +483,7 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
     }
   }
   const Pass2Anchors<F, T> an2 = fft3_pass2_load<F, T>(tw2, t);
+  if constexpr (PRE_BARRIER) lds_barrier();
   fft3_ex1_write<F, 0>(v, lds, cols);
   lds_barrier();
   double S = 0.0;
@@ -597,6 +688,83 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
       unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
       emit_tails<F, T>(z, 0u, thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
     }
+  }
+}
+
+// One correlation (template j of the launch's bank slice, spectrum row `row`)
+// by one workgroup of corr_loop_kernel: corr_kernel's stages, with the barrier
+// before the exchange that looping needs.  (corr_kernel keeps its own copy of
+// this sequence: sharing the function changed its register schedule.)
+template <typename T, typename TW, class F, bool DENSE, int G>
+__device__ __forceinline__ void corr_item(
+    uint32_t j, uint32_t row, T* lds, double* red, const TW* __restrict__ bank, const cx<T>* __restrict__ yspec,
+    const uint32_t* __restrict__ seg_ids, const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1,
+    const cx<T>* __restrict__ tw2, double kappa, double* __restrict__ sigma_out, tail_rec_t<T>* __restrict__ tails,
+    unsigned long long* __restrict__ counter, uint64_t cap, unsigned long long* __restrict__ proj,
+    const uint64_t* __restrict__ proj_off, double kappa_hi, T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total,
+    uint32_t row0, int t) {
+  constexpr int M = F::M;
+  constexpr double N = 2.0 * M;
+  const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row0 + row);
+  const uint32_t jg = j0 + j;  // template id in the whole bank
+  const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
+  const rsrc_t rY = make_rsrc(yspec + uint64_t(row) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
+  cx<T> v[F::P];
+  double acc = 0.0;
+  uint32_t cols[F::C1];
+#pragma unroll
+  for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
+  // 32 points per thread: these kernels hold 4 waves per SIMD whatever their
+  // register count below 128, so the early twiddle request is free
+  corr_pre<F, MAP_MIRROR, G, T, TW, (F::P >= 32)>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
+  const double S = corr_ifft<F, T, 1, true>(v, lds, red, cols, tw1, tw2, t, acc);
+  const double rootS = sqrt(S);
+  if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
+  auto z = [&](int i) { return v[i]; };
+  if constexpr (DENSE) {
+    const rsrc_t rr = make_rsrc(rho_dense + (uint64_t(s) * k_total + jg) * uint64_t(2 * M), uint32_t(M) * uint32_t(sizeof(cx<T>)));
+    emit_dense<F, T>(z, 0u, N, rr, t);
+  } else {
+    const T thr = T(kappa * rootS);
+    const T thr_hi = kappa_hi > 0.0 ? T(kappa_hi * rootS) : T(INFINITY);
+    T mx = T(0);
+#pragma unroll
+    for (int i = 0; i < F::P; ++i) mx = fmax(mx, fmax(fabs(v[i].x), fabs(v[i].y)));
+    const bool any = (mx > thr) && (rootS > 0.0);
+    if (__ballot(any)) {
+      unsigned long long* prow = proj ? proj + proj_off[row] : nullptr;
+      emit_tails<F, T>(z, 0u, thr, thr_hi, any, s, jg, N, tails, counter, cap, prow, rootS, t);
+    }
+  }
+}
+
+// The same correlations with fewer workgroups, each looping over items
+// b, b + gridDim.x, b + 2 gridDim.x, ... < n_items of the tile_map order (a
+// multiple of 8 workgroups keeps every item on the XCD tile_map gives it).
+// The waves of a workgroup need not finish one correlation together: a wave
+// done early loads and multiplies the next correlation's spectra while the
+// others finish the last one, up to the barrier before the next exchange, so
+// the spectrum latency at the start of a correlation and the spread of its
+// waves at the end overlap.
+template <typename T, typename TW, class F, bool DENSE, int G>
+__global__ __launch_bounds__(F::NT) void corr_loop_kernel(
+    const TW* __restrict__ bank, const cx<T>* __restrict__ yspec, const uint32_t* __restrict__ seg_ids,
+    const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
+    uint32_t K, uint32_t n_rows, uint32_t tile, double kappa, double* __restrict__ sigma_out,
+    tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
+    unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
+    T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0, uint32_t n_items) {
+  __shared__ T lds[F::LDS_ELEMS];
+  __shared__ double red[F::NW];
+  for (uint32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+    uint32_t j, row;
+    if (!tile_map(i, K, n_rows, tile, j, row)) continue;
+    // an opaque copy of the thread index per item: the lane addresses derived from it
+    // are formed where used, not hoisted out of the loop and kept (spilled) across it
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    corr_item<T, TW, F, DENSE, G>(j, row, lds, red, bank, yspec, seg_ids, tw_u, tw1, tw2, kappa, sigma_out,
+                                        tails, counter, cap, proj, proj_off, kappa_hi, rho_dense, j0, k_total, row0, t);
   }
 }
 

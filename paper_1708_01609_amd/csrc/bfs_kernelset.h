@@ -37,6 +37,7 @@ struct FwdArgs {
   const void* tw2;
   void* out;
   double* energy;
+  uint32_t zs;  // > 1: segments' transforms split zs ways (sub-sequence b mod zs of segment b / zs)
 };
 
 struct CorrArgs {
@@ -67,6 +68,7 @@ struct CorrArgs {
   int taper;
   int sym;
   uint32_t rows;
+  uint32_t cus;  // compute units of the device (looping sets size their grid by it; 0: one item per workgroup)
 };
 
 struct KernelSet {
@@ -75,6 +77,7 @@ struct KernelSet {
   int M;             // N/2 (= FM, or 2 FM when split)
   int split;
   int G;             // load-group depth of the product stage
+  int loop;          // 1: workgroups loop over correlations (corr_loop_kernel)
   size_t real_size;  // sizeof(T)
   size_t spec_size;  // bytes of one stored template spectrum element
   size_t tail_size;  // bytes of one tail record the kernels write
@@ -89,13 +92,17 @@ struct KernelSet {
   hipError_t (*export_y)(uint32_t count, hipStream_t st, const void* y, double* out);
   // fused synthesis (FP32 cubic sets with load group 4; null otherwise): the correlation with
   // each template made on chip, and the segment spectra's copy in the fused layout
+  // the join of segment transforms split JOIN_A ways (JOIN_A = M / 1024 > 1, unsplit sets; 0: none)
+  hipError_t (*join)(uint32_t count, hipStream_t st, const void* in, void* out, const void* tw_u);
+  int join_a;
   hipError_t (*corr_fused)(bool dense, uint32_t S, hipStream_t st, const CorrArgs& a);
   hipError_t (*permute_y)(uint32_t count, hipStream_t st, const void* y, void* out);
   int fused_rows_max;  // largest pruned first-pass row count built below the full R1
 };
 
-template <typename T, typename TW, class F, int SPLIT, int G>
+template <typename T, typename TW, class F, int SPLIT, int G, int LOOP = 0>
 struct Impl {
+  static_assert(!LOOP || !SPLIT, "looping workgroups are built for unsplit transforms");
   static constexpr int M = F::M * (SPLIT ? 2 : 1);
   static hipError_t fwd(int src, uint32_t batch, hipStream_t st, const FwdArgs& a) {
     const dim3 grid(batch * (SPLIT ? 2u : 1u)), block(F::NT);
@@ -104,16 +111,16 @@ struct Impl {
     auto* out = static_cast<cx<T>*>(a.out);
     if (src == SRC_SAMPLES)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
     else if (src == SRC_CHIRP)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
     else if (src == SRC_CHIRP_SYM)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP_SYM>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
     else
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
     return hipGetLastError();
   }
   static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,
@@ -163,6 +170,10 @@ struct Impl {
         launch_fused<DENSE, FUSED_NZ>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
       else
         launch_fused<DENSE, F::R1>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
+    } else if constexpr (LOOP && !PAIR && !SPLIT) {
+      hipLaunchKernelGGL((corr_loop_kernel<T, TW, F, DENSE, G>), dim3(loop_grid(blocks, a.cus)), dim3(F::NT), 0, st,
+                         bank, y, seg_ids, tu, t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap,
+                         a.proj, proj_off, a.kappa_hi, rho, j0, a.K, row0, blocks);
     } else if constexpr (PAIR && !SPLIT)
       hipLaunchKernelGGL((pair_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
@@ -175,6 +186,23 @@ struct Impl {
       hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
+  }
+  // Looping sets: as many workgroups as the device holds at once (a multiple of 8, so
+  // each keeps the XCD of its items), at most one per item.
+  static uint32_t loop_grid(uint32_t items, uint32_t cus) {
+    static int per_cu = -1;
+    if (per_cu < 0) {
+      int occ = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, corr_loop_kernel<T, TW, F, false, G>, F::NT, 0) !=
+          hipSuccess) {
+        (void)hipGetLastError();
+        occ = 1;
+      }
+      per_cu = std::max(occ, 1);
+    }
+    if (!cus) return items;
+    const uint32_t g = std::max<uint32_t>(8, (cus * uint32_t(per_cu)) & ~7u);
+    return std::min(items, g);
   }
   // 1-D grids in the XCD-aware order of tile_map, 8 ceil(K/8) S workgroups in all.  A
   // launch holds at most MAX_ITEMS work items (the dispatch's grid size is a 32-bit count
@@ -223,6 +251,16 @@ struct Impl {
     if (!a.f0 || !a.fdot || !a.len || !a.norm || a.rows < 1 || a.rows > uint32_t(F::R1)) return hipErrorInvalidValue;
     return corr_t<MODE_FUSED>(dense, S, st, a);
   }
+  static constexpr int JOIN_A = (!SPLIT && M >= 2048 && M <= 32768) ? M / 1024 : 0;
+  static hipError_t join(uint32_t count, hipStream_t st, const void* in, void* out, const void* tw_u) {
+    if constexpr (JOIN_A > 1) {
+      const dim3 grid((1024 + 255) / 256, count);
+      hipLaunchKernelGGL((fft_join_kernel<T, JOIN_A>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(in),
+                         static_cast<cx<T>*>(out), static_cast<const cx<T>*>(tw_u), uint32_t(M));
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
   static hipError_t permute_y(uint32_t count, hipStream_t st, const void* y, void* out) {
     if constexpr (FUSED) {
       const dim3 grid((M + 255) / 256, count);
@@ -245,10 +283,10 @@ struct Impl {
     return hipGetLastError();
   }
   static const KernelSet* get() {
-    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, sizeof(T), sizeof(TW), sizeof(tail_rec_t<T>),
-                                 &fwd, &unpack_bank, &unpack_y, &corr, SPLIT ? nullptr : &corr_pair, &export_bank,
-                                 &export_y, FUSED ? &corr_fused : nullptr, FUSED ? &permute_y : nullptr,
-                                 FUSED_NZ};
+    static const KernelSet ks = {F::R1, F::R2, F::R3, F::NT, F::M, M, SPLIT, G, LOOP, sizeof(T), sizeof(TW),
+                                 sizeof(tail_rec_t<T>), &fwd, &unpack_bank, &unpack_y, &corr, SPLIT ? nullptr : &corr_pair, &export_bank,
+                                 &export_y, JOIN_A > 1 ? &join : nullptr, JOIN_A, FUSED ? &corr_fused : nullptr,
+                                 FUSED ? &permute_y : nullptr, FUSED_NZ};
     return &ks;
   }
 };
@@ -258,9 +296,9 @@ constexpr int MAX_CANDIDATES = 8;
 struct Candidates {
   const KernelSet* ks[MAX_CANDIDATES];
   int count = 0;
-  template <typename T, typename TW, class F, int SPLIT, int G>
+  template <typename T, typename TW, class F, int SPLIT, int G, int LOOP = 0>
   void add() {
-    if (count < MAX_CANDIDATES) ks[count++] = Impl<T, TW, F, SPLIT, G>::get();
+    if (count < MAX_CANDIDATES) ks[count++] = Impl<T, TW, F, SPLIT, G, LOOP>::get();
   }
 };
 
@@ -310,6 +348,8 @@ Candidates candidates_t(uint32_t m) {
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 8>();
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 4>();
         c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 2>();
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 8, 1>();
+        c.add<T, TW, Fft3<T, 32, 32, 32, 1024>, 0, 4, 1>();
       }
       break;
     case 65536:

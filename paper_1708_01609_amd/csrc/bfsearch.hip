@@ -164,6 +164,13 @@ struct SizePlan {
   const void* tw2 = nullptr;
   uint64_t bank_bytes = 0, tab_bytes = 0;
   uint32_t fused_rows = 0;  // fused plans: nonzero input rows of the forward transform's first pass
+  // segment transforms split ks->join_a ways: the kernel set and tables of the length-1024
+  // sub-transforms (null when the length's set has no join)
+  const KernelSet* sub = nullptr;
+  void* sub_tables = nullptr;
+  const void* sub_tw1 = nullptr;
+  const void* sub_tw2 = nullptr;
+  uint64_t sub_tab_bytes = 0;
 };
 
 }  // namespace
@@ -176,6 +183,7 @@ struct bfs_plan {
   uint64_t cap = 0;
   std::vector<SizePlan> sizes;  // ascending N: sizes[i].N = n_min << i
   size_t rec_bytes = sizeof(tail_rec);  // tail record the kernels write: 24 bytes for FP64, else 16
+  uint32_t cus = 0;                     // compute units of the device
   uint64_t bank_bytes = 0, plan_bytes = 0, budget = 0;
   bool graph = false;
   bool project = false;  // per-lag max projection instead of the tail list
@@ -270,6 +278,7 @@ void free_plan(bfs_plan* p) {
   for (auto& sp : p->sizes) {
     if (sp.bank) (void)hipFree(sp.bank);
     if (sp.tables) (void)hipFree(sp.tables);
+    if (sp.sub_tables) (void)hipFree(sp.sub_tables);
   }
   if (p->f0_dev) (void)hipFree(p->f0_dev);
   if (p->fparams) (void)hipFree(p->fparams);
@@ -363,6 +372,59 @@ bfs_status set_tables(SizePlan& sp, const KernelSet* ks) {
   return BFS_OK;
 }
 
+// Tables of the length-1024 sub-transforms of a split segment transform
+// (their own length 2048 as a real transform).
+bfs_status set_sub_tables(SizePlan& sp) {
+  const KernelSet& ks = *sp.sub;
+  bfs_status st = alloc_checked(&sp.sub_tables, sp.sub_tab_bytes);
+  if (st != BFS_OK) return st;
+  hipError_t e;
+  if (ks.real_size == sizeof(double)) {
+    auto tab = make_tables<double>(ks, 2048);
+    e = hipMemcpy(sp.sub_tables, tab.data(), sp.sub_tab_bytes, hipMemcpyHostToDevice);
+  } else {
+    auto tab = make_tables<float>(ks, 2048);
+    e = hipMemcpy(sp.sub_tables, tab.data(), sp.sub_tab_bytes, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return BFS_ERR_HIP;
+  const char* tb = static_cast<const char*>(sp.sub_tables);
+  sp.sub_tw1 = tb + 2ull * ks.M * ks.real_size;
+  sp.sub_tw2 = tb + 2ull * (uint64_t(ks.M) + uint64_t(ks.FM)) * ks.real_size;
+  return BFS_OK;
+}
+
+// Queue the forward transform of `count` segments of one length into the
+// packed half spectra y ([count][M]): segment i's samples at seg_ptr[i], or
+// src + i src_stride when seg_ptr is null.  Lengths whose set joins split
+// transforms run as count x join_a length-1024 transforms (many small
+// workgroups instead of one large one per segment), the join and the unpack;
+// the others as one workgroup per segment (two halves at the split length)
+// and the unpack.  z: scratch of the same size as y (split and joined paths).
+bfs_status queue_segment_fft(const SizePlan& sp, uint32_t count, const uint64_t* seg_ptr, const void* src,
+                             uint64_t src_stride, void* y, void* z, hipStream_t st) {
+  const KernelSet& ks = *sp.ks;
+  FwdArgs a{};
+  a.seg_ptr = seg_ptr;
+  a.src = src;
+  a.src_stride = src_stride;
+  if (ks.join && sp.sub) {
+    a.tw1 = sp.sub_tw1;
+    a.tw2 = sp.sub_tw2;
+    a.out = z;
+    a.zs = uint32_t(ks.join_a);
+    HIP_TRY(sp.sub->fwd(SRC_SAMPLES, count * uint32_t(ks.join_a), st, a));
+    HIP_TRY(ks.join(count, st, z, y, sp.tw_u));
+    HIP_TRY(ks.unpack_y(count, st, y, y, sp.tw_u));
+    return BFS_OK;
+  }
+  a.tw1 = sp.tw1;
+  a.tw2 = sp.tw2;
+  a.out = ks.split ? z : y;
+  HIP_TRY(ks.fwd(SRC_SAMPLES, count, st, a));
+  HIP_TRY(ks.unpack_y(count, st, a.out, y, sp.tw_u));
+  return BFS_OK;
+}
+
 // Autotuner: time every candidate kernel set of one size on the resident bank
 // (up to 4096 templates against a zero segment spectrum: the work of a
 // correlation does not depend on the data, only the rare tail writes do),
@@ -398,6 +460,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
     a.tails = tails;
     a.counter = static_cast<unsigned long long*>(counter);
     a.cap = 1;
+    a.cus = p->cus;
     float ms_min = 0.f;
     for (int r = 0; r < 4 && st == BFS_OK; ++r) {
       if (hipEventRecord(e0, s) != hipSuccess || c.ks[i]->corr(false, 1, s, a) != hipSuccess ||
@@ -439,6 +502,7 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
     a.tails = tails;
     a.counter = static_cast<unsigned long long*>(counter);
     a.cap = 1;
+    a.cus = p->cus;
     float ms_min = 0.f;
     for (int r = 0; r < 4 && st == BFS_OK; ++r) {
       if (hipEventRecord(e0, s) != hipSuccess || sp.ks->corr(false, TUNE_SEGS, s, a) != hipSuccess ||
@@ -584,8 +648,12 @@ void size_plans(bfs_plan* p, const bfs_plan_desc* d, bool fused) {
     }
     for (int i = 0; i < c.count; ++i)
       sp.tab_bytes = std::max<uint64_t>(sp.tab_bytes, table_elems(*c.ks[i]) * c.ks[i]->real_size);
+    if (sp.ks->join) {
+      sp.sub = pick_kernels(d->precision, 1024);
+      if (sp.sub) sp.sub_tab_bytes = table_elems(*sp.sub) * sp.sub->real_size;
+    }
     p->bank_bytes += sp.bank_bytes;
-    p->plan_bytes += sp.bank_bytes + sp.tab_bytes;
+    p->plan_bytes += sp.bank_bytes + sp.tab_bytes + sp.sub_tab_bytes;
     p->sizes.push_back(sp);
   }
   if (fused) p->plan_bytes += uint64_t(p->K) * (2 * sizeof(double) + sizeof(uint32_t) + sizeof(float));
@@ -748,7 +816,7 @@ bfs_status make_layout(const bfs_plan* p, const uint32_t* lens, uint32_t S, Layo
     g.first = uint32_t(first);
     const uint64_t gbytes = uint64_t(cnt) * sp.M * 2 * sp.ks->real_size;
     ybytes += (gbytes + 255) & ~uint64_t(255);
-    if (sp.ks->split) zbytes = std::max(zbytes, gbytes);
+    if (sp.ks->split || (sp.ks->join && sp.sub)) zbytes = std::max(zbytes, gbytes);
     first += cnt;
     L.groups.push_back(g);
   }
@@ -817,14 +885,9 @@ bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   char* ybase = static_cast<char*>(b->y);
   for (const Group& g : L.groups) {
     const KernelSet& ks = *g.sp->ks;
-    FwdArgs a{};
-    a.seg_ptr = dptr + g.first;
-    a.tw1 = g.sp->tw1;
-    a.tw2 = g.sp->tw2;
     void* yg = ybase + g.y_off;
-    a.out = ks.split ? b->z : yg;
-    HIP_TRY(ks.fwd(SRC_SAMPLES, g.count, st, a));
-    HIP_TRY(ks.unpack_y(g.count, st, a.out, yg, g.sp->tw_u));
+    const bfs_status rs = queue_segment_fft(*g.sp, g.count, dptr + g.first, nullptr, 0, yg, b->z, st);
+    if (rs != BFS_OK) return rs;
     if (p->fused) HIP_TRY(ks.permute_y(g.count, st, yg, ybase + g.yf_off));
   }
   return BFS_OK;
@@ -877,6 +940,7 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
     c.proj = project ? b->proj : nullptr;
     c.proj_off = project ? dpoff + g.first : nullptr;
     c.rho = rho;
+    c.cus = p->cus;
     if (p->fused) {
       set_fused_args(p, *g.sp, c);
       if (first) {  // a slice of the bank: its templates' parameters
@@ -1292,6 +1356,12 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     delete p;
     return BFS_ERR_HIP;
   }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d->device) != hipSuccess || cus < 0) {
+    (void)hipGetLastError();
+    cus = 0;
+  }
+  p->cus = uint32_t(cus);
   // the no-allocation entry point's scratch area on this device (looked up once per
   // device; a failed lookup only disables that entry point)
   if (scratch_address(d->device, &p->scratch) != BFS_OK) p->scratch = nullptr;
@@ -1314,6 +1384,7 @@ bfs_status bfsearch_plan(const bfs_plan_desc* d, bfs_plan** out) {
     if (!p->fused) st = alloc_checked(&sp.bank, sp.bank_bytes);
     if (st == BFS_OK) st = alloc_checked(&sp.tables, sp.tab_bytes);
     if (st == BFS_OK) st = set_tables(sp, sp.ks);
+    if (st == BFS_OK && sp.sub) st = set_sub_tables(sp);
     if (st != BFS_OK) break;
   }
   if (st == BFS_OK) st = p->fused ? build_fused(p, d) : build_banks(p, d);
@@ -1370,6 +1441,7 @@ bfs_status bfsearch_plan_kernel_info(const bfs_plan* p, uint32_t n, bfs_kernel_i
   out->tile = sp->tile;
   for (int i = 0; i < N_TILES; ++i) out->tile_us[i] = sp->tile_us[i];
   out->fused = p->fused ? 1u : 0u;
+  out->loop = uint32_t(sp->ks->loop);
   out->fused_rows = sp->fused_rows;
   return BFS_OK;
 }
@@ -1424,11 +1496,12 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   if (!sp) return BFS_ERR_INVALID_ARG;
   if (p->pairs && (S & 1u)) return BFS_ERR_INVALID_ARG;
   const KernelSet& ks = *sp->ks;
-  // segment spectra, then their fused-layout copy (fused plans) or (split length) the
-  // transform scratch
+  // segment spectra, then a scratch of the same size: the transform's (split and joined
+  // segment transforms) and the fused-layout copy (fused plans) in turn
   const uint64_t spec_bytes = uint64_t(S) * sp->M * 2 * ks.real_size;
   const uint64_t y_bytes = (spec_bytes + 255) & ~uint64_t(255);
-  const uint64_t z_bytes = (ks.split || p->fused) ? spec_bytes : 0;
+  const bool joined = ks.join && sp->sub;
+  const uint64_t z_bytes = (ks.split || p->fused || joined) ? spec_bytes : 0;
   if (y_bytes + z_bytes > NOALLOC_SCRATCH_BYTES) return BFS_ERR_SCRATCH_LIMIT;
   if (!p->scratch) return BFS_ERR_HIP;
   int cur = -1;
@@ -1436,20 +1509,14 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   if (cur != p->device) HIP_TRY(hipSetDevice(p->device));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   char* y = static_cast<char*>(p->scratch);
-  void* z = (ks.split || p->fused) ? y + y_bytes : nullptr;
+  void* z = (ks.split || p->fused || joined) ? y + y_bytes : nullptr;
   auto* counter = reinterpret_cast<unsigned long long*>(count_dev);
   // the count starts at zero (a fill kernel, so the call can be captured in a graph)
   hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, counter, uint64_t(1), 0ull);
   HIP_TRY(hipGetLastError());
-  FwdArgs a{};
-  a.src = y_dev;
-  a.src_stride = seg_len;
-  a.seg_ptr = nullptr;  // segments packed back to back
-  a.tw1 = sp->tw1;
-  a.tw2 = sp->tw2;
-  a.out = ks.split ? z : y;
-  HIP_TRY(ks.fwd(SRC_SAMPLES, S, st, a));
-  HIP_TRY(ks.unpack_y(S, st, a.out, y, sp->tw_u));
+  // segments packed back to back
+  const bfs_status rs = queue_segment_fft(*sp, S, nullptr, y_dev, seg_len, y, z, st);
+  if (rs != BFS_OK) return rs;
   if (p->fused) HIP_TRY(ks.permute_y(S, st, y, z));
   CorrArgs c{};
   c.bank = sp->bank;
@@ -1466,6 +1533,7 @@ bfs_status bfsearch_filter_noalloc(bfs_plan* p, const void* y_dev, uint32_t seg_
   c.tails = tails_dev;
   c.counter = counter;
   c.cap = tail_capacity;
+  c.cus = p->cus;
   if (p->fused) {
     set_fused_args(p, *sp, c);
     HIP_TRY(ks.corr_fused(false, S, st, c));

@@ -112,7 +112,7 @@ def test_plan_desc_layout_matches_header(bfs):
     assert off["flags"] == off["device"] + 4 and off["candidate"] == off["flags"] + 4
     assert off["tile"] == off["candidate"] + 4 and off["kappa_hi"] % 8 == 0 and off["kappa_hi"] > off["tile"]
     assert ctypes.sizeof(bfs.PlanDesc) % 8 == 0
-    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4 + 2 * 4
+    assert ctypes.sizeof(bfs.KernelInfo) == 9 * 4 + 8 * 4 + 4 + 5 * 4 + 3 * 4
 
 
 def test_fused_plans_are_checked_on_the_host(bfs):

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from synthetic import get_workload, make_segment
-from tests.parity import TOL, tol_scale
+from tests.parity import TOL, sigma_floor, tol_scale
 
 pytestmark = pytest.mark.gpu
 
@@ -132,6 +132,9 @@ def test_projection_uneven_graph_matches_eager_and_oracle(bfs):
     tau = np.array([W.taus[j % 3] for j in range(64)])
     temps = oracle.template_bank(f0, fd, tau, W.fs)
     out = oracle.search([y.astype(np.float64) for y in segs], temps, W.kappa)
-    common, band = compare_projection(eager, segs, temps, W.kappa, TOL["f32"], out)
+    # the grid's lowest chirps lie far outside the data band (sigma ~1e-3 of the input
+    # scale): their tolerance scales with sigma_floor, as in the dense parity tests
+    floor = np.array([[sigma_floor(t, y) for t in temps] for y in segs])
+    common, band = compare_projection(eager, segs, temps, W.kappa, TOL["f32"], out, floor)
     print(f"uneven projection: {len(eager)} lags, {common} common, {band} band-only")
     assert common > 0 and band <= max(2, common // 100)

@@ -79,7 +79,8 @@ def test_noalloc_rejects_what_does_not_fit(bfs):
     n = 1 << 16
     grid = bfs.Grid(2, 2, (350.0, 2000.0), (-500.0, 500.0), (1.0,))
     with bfs.Plan(n, 4096.0, kappa=5.0, grid=grid, precision="f32") as plan:
-        s_max = bfs.NOALLOC_SCRATCH_BYTES // (n * 4)  # FP32 spectra: 4 bytes per sample
+        # FP32 spectra take 4 bytes per sample, and the segment transform a scratch of that size
+        s_max = bfs.NOALLOC_SCRATCH_BYTES // (2 * n * 4)
         y = torch.zeros((s_max + 1, n), dtype=torch.float32, device="cuda:0")
         tails_buf = torch.empty(16 * plan.tail_dtype.itemsize, dtype=torch.uint8, device="cuda:0")
         count = torch.zeros(1, dtype=torch.int64, device="cuda:0")
