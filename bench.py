@@ -514,7 +514,9 @@ def main():
         "roofline": {
             "bound": "alu",
             "kernel": ("corr_fused_kernel (synthesis, forward FFT, product, sigma, inverse FFT, threshold)"
-                       if args.fused else "corr_kernel (fused product, sigma, inverse FFT, threshold, compaction)"),
+                       if args.fused else
+                       ("corr_loop_kernel" if info["kernel"].get("loop") else "corr_kernel")
+                       + " (fused product, sigma, inverse FFT, threshold, compaction)"),
             "achieved": r["achieved_tflops"],
             "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s",

@@ -234,6 +234,51 @@ __device__ __forceinline__ void fft3_pass2(cx<T>* v, const cx<T>* __restrict__ t
   fft3_pass2<F, DIR, T>(v, fft3_pass2_load<F, T>(tw2, t));
 }
 
+// v[i] *= tab[i stride + e] for i = 1..R-1 (conjugated for DIR < 0), with tab
+// an LDS table: every twiddle is read (one ds_read each, offsets as
+// immediates from one base register), none is formed by products.
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void twiddle_apply_lds(cx<T>* v, const cx<T>* tab, uint32_t stride, uint32_t e) {
+  // the column's LDS byte address, opaque: one register, and each row's read
+  // takes its offset as an immediate (the table may lie beyond the 16-bit
+  // offset range from LDS address 0)
+  using lcx = __attribute__((address_space(3))) const cx<T>;
+  uint32_t a = uint32_t(uintptr_t((lcx*)(tab + e)));
+  asm volatile("" : "+v"(a));
+  lcx* col = (lcx*)(uintptr_t(a));
+#pragma unroll
+  for (int i = 1; i < R; ++i) {
+    cx<T> w = {col[i * stride].x, col[i * stride].y};
+    if constexpr (DIR < 0) w.y = -w.y;
+    v[i] = cmul(v[i], w);
+  }
+}
+
+// Pass 2 with the twiddle table tw2 ([R2][R3], exp(+2 pi i m0 j1 / S1)) held in
+// LDS.  fft3_tw2_stage copies the table; a workgroup barrier of the caller
+// (exchange 1) orders the copy before the reads.  Used by the 1024-thread
+// shapes (32 points per thread, one inverse transform per workgroup), where it
+// measured faster; smaller workgroups pay the per-correlation copy for fewer
+// products saved, and the split kernel's two transforms measured slower.
+template <class F>
+constexpr bool tw2_in_lds() {
+  return F::NT == 1024;
+}
+template <class F, typename T>
+__device__ __forceinline__ void fft3_tw2_stage(cx<T>* tw2s, const cx<T>* __restrict__ tw2, int t) {
+  for (int i = t; i < F::R2 * F::R3; i += F::NT) tw2s[i] = tw2[i];
+}
+template <class F, int DIR, typename T>
+__device__ __forceinline__ void fft3_pass2_tab(cx<T>* v, const cx<T>* tw2s, int t) {
+#pragma unroll
+  for (int c = 0; c < F::C2; ++c) {
+    dft<F::R2, DIR, T>(&v[c * F::R2]);
+    sched_fence();
+    twiddle_apply_lds<F::R2, DIR, T>(&v[c * F::R2], tw2s, F::R3, uint32_t(t + F::NT * c) % F::R3);
+    sched_fence();
+  }
+}
+
 template <class F, typename T>
 __device__ __forceinline__ void fft3_ex2(cx<T>* v, T* lds, int t) {
   const int lane = t & 63, wave = t >> 6;

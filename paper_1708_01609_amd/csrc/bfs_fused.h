@@ -191,10 +191,12 @@ __device__ __forceinline__ void dft_pruned(cx<T>* v) {
 }
 
 // Forward transform of one template on chip (DIR = -1), leaving Z_k, k = col(t) + S1 k2,
-// in v[k2].  rows: the first NZ input rows (k2 < NZ) of thread t's column t.
+// in v[k2].  rows: the first NZ input rows (k2 < NZ) of thread t's column t.  tw2s:
+// the LDS copy of the pass-2 table where tw2_in_lds<F>() (ordered before use by
+// exchange 1's barriers), else the table itself.
 template <class F, int NZ, typename T>
 __device__ __forceinline__ void fused_forward(cx<T>* v, T* lds, const cx<T>* __restrict__ tw1,
-                                              const cx<T>* __restrict__ tw2, int t, int n0, int m0) {
+                                              const cx<T>* tw2s, int t, int n0, int m0) {
   constexpr int R = F::R1;
   const uint32_t colf[1] = {uint32_t(t)};
   {  // pass 1: pruned DFT over the rows, then w_M^(-n0 col)
@@ -203,8 +205,10 @@ __device__ __forceinline__ void fused_forward(cx<T>* v, T* lds, const cx<T>* __r
     twiddle_apply<R, -1, T>(v, an);
     sched_fence();
   }
-  // pass-2 item: (n0, j1) with j1 = m0 (the thread's own pass-3 index)
-  const Anchors<R, T> an2 = twiddle_load<R, T>(tw2, F::R3, uint32_t(m0));
+  // pass-2 item: (n0, j1) with j1 = m0 (the thread's own pass-3 index); table
+  // anchors are requested before the exchange, whose barriers hide the wait
+  Anchors<R, T> an2{};
+  if constexpr (!tw2_in_lds<F>()) an2 = twiddle_load<R, T>(tw2s, F::R3, uint32_t(m0));
   auto ex1_read = [&](int pl) {
 #pragma unroll
     for (int j2 = 0; j2 < R; ++j2) {
@@ -223,7 +227,11 @@ __device__ __forceinline__ void fused_forward(cx<T>* v, T* lds, const cx<T>* __r
   lds_barrier();
   dft<R, -1, T>(v);
   sched_fence();
-  twiddle_apply<R, -1, T>(v, an2);
+  if constexpr (tw2_in_lds<F>()) {
+    twiddle_apply_lds<R, -1, T>(v, tw2s, F::R3, uint32_t(m0));
+  } else {
+    twiddle_apply<R, -1, T>(v, an2);
+  }
   sched_fence();
   // exchange 2 inside the n0 group (one wave): write [m][j1 = m0], read [m0][j1]
   T* grp = lds + n0 * R * (R + 1);
@@ -251,50 +259,32 @@ __device__ __forceinline__ void fused_forward(cx<T>* v, T* lds, const cx<T>* __r
 // Unpack Z (complex FFT of z_n = w_{2n} + i w_{2n+1}) into the packed real
 // spectrum of w, scaled by sc, in place:
 //   E_k = (Z_k + conj Z_{M-k}) / 2,  O_k = -i (Z_k - conj Z_{M-k}) / 2,
-//   W_k = E_k + exp(-2 pi i k / N) O_k;  slot 0 of column 0: (W_0, W_M) =
-//   (Re Z_0 + Im Z_0, Re Z_0 - Im Z_0).
-// Partners as in the repack: lane l ^ 32 at register R-1-k2, columns 0 and
-// S1/2 within their own thread.  bu = exp(2 pi i col / N).
+//   W_k = E_k + s_k O_k,  s_k = exp(-2 pi i k / N);  slot 0 of column 0:
+//   (W_0, W_M) = (Re Z_0 + Im Z_0, Re Z_0 - Im Z_0).
+// E_{M-k} = conj E_k, O_{M-k} = conj O_k and s_{M-k} = -conj s_k give
+// W_{M-k} = conj(E_k - s_k O_k): one lane forms both values of a pair
+// (mirror_pairs; partners as in the repack, columns 0 and S1/2 within their
+// own lane, bin M/2 of column 0 with itself: W = sc conj Z).
+// bu = exp(2 pi i col / N).
 template <class F, typename T>
 __device__ __forceinline__ void fused_unpack(cx<T>* v, const cx<T>& bu, T sc, int t) {
-  constexpr int R = F::R1;
-  const int lane = t & 63;
-  const bool wave0 = __builtin_amdgcn_readfirstlane(t) < 64;
-  cx<T> carry = {T(0), T(0)};
-  static_for<R / 2>([&](auto kc) {
-    constexpr int r1 = decltype(kc)::value;
-    constexpr int r2 = R - 1 - r1;
-    const cx<T> A = v[r1], B = v[r2];
-    cx<T> PA, PB;
-    partner_pair(A, B, PA, PB);
-    if (wave0) {
-      // column 0 (lane 0): register r pairs with R - r (register 0 with itself);
-      // column S1/2 (lane 32): r1 with r2
-      const cx<T> a0 = (r1 == 0) ? A : carry;
-      const cx<T> b0 = (r1 + 1 == r2) ? B : v[r1 + 1];
-      PA.x = lane == 0 ? a0.x : (lane == 32 ? B.x : PA.x);
-      PA.y = lane == 0 ? a0.y : (lane == 32 ? B.y : PA.y);
-      PB.x = lane == 0 ? b0.x : (lane == 32 ? A.x : PB.x);
-      PB.y = lane == 0 ? b0.y : (lane == 32 ? A.y : PB.y);
-      carry = B;
-    }
-    auto unpack = [&](const cx<T>& zk, const cx<T>& zp, const cx<T>& tk) {
-      const cx<T> e = {T(0.5) * (zk.x + zp.x), T(0.5) * (zk.y - zp.y)};
-      const cx<T> od = {T(0.5) * (zk.y + zp.y), T(-0.5) * (zk.x - zp.x)};
-      const cx<T> wo = cmulc(tk, od);  // exp(-2 pi i k / N) O_k
-      return cx<T>{(e.x + wo.x) * sc, (e.y + wo.y) * sc};
-    };
-    cx<T> w1 = unpack(A, PA, rot<r1, 2 * R, +1>(bu));
-    if constexpr (r1 == 0) {
-      if (wave0 && lane == 0) w1 = {(A.x + A.y) * sc, (A.x - A.y) * sc};
-    }
-    v[r1] = w1;
-    v[r2] = unpack(B, PB, rot<r2, 2 * R, +1>(bu));
-    pin(v[r1]);
-    pin(v[r2]);
-    if constexpr (r1 % 4 == 3) sched_fence();
-  });
-  sched_fence();
+  static_assert(F::C1 == 1, "one column per thread");
+  const T hs = T(0.5) * sc;
+  const cx<T> z0 = v[0];  // lane 0 of wave 0: Z_0
+  mirror_pairs<F, true, T>(
+      v, t, cx<T>{T(0), T(0)}, [](int) {},
+      [&](int, auto r1c, const cx<T>& A, const cx<T>& bp, cx<T>& wa, cx<T>& wb) {
+        constexpr int r1 = decltype(r1c)::value;
+        const cx<T> e = {A.x + bp.x, A.y - bp.y};   // 2 E_k
+        const cx<T> od = {A.y + bp.y, bp.x - A.x};  // 2 O_k
+        const cx<T> so = cmulc(rot<r1, 2 * F::R1, +1>(bu), od);
+        wa = cx<T>{(e.x + so.x) * hs, (e.y + so.y) * hs};
+        wb = cx<T>{(e.x - so.x) * hs, (so.y - e.y) * hs};  // W_{M-k}
+      },
+      [&](const cx<T>& m) { return cx<T>{m.x * sc, -m.y * sc}; });
+  if (__builtin_amdgcn_readfirstlane(t) < 64)
+    v[0] = lane_sel(1ull, v[0], cx<T>{(z0.x + z0.y) * sc, (z0.x - z0.y) * sc});
+  pin(v[0]);
 }
 
 // Product with the segment spectrum (fused layout, loads G registers ahead) and the
@@ -358,9 +348,12 @@ __global__ __launch_bounds__(F::NT) void corr_fused_kernel(
   constexpr double N = 2.0 * M;
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
+  constexpr bool TWL = tw2_in_lds<F>();
+  __shared__ cx<T> tw2s[TWL ? F::R2 * F::R3 : 1];
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
+  if constexpr (TWL) fft3_tw2_stage<F>(tw2s, tw2, t);
   const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row0 + row);
   const uint32_t jg = j0 + j;
   int n0 = 0, m0 = 0;
@@ -391,7 +384,7 @@ __global__ __launch_bounds__(F::NT) void corr_fused_kernel(
     }
   }
   // 2-3. forward transform and unpack into the unit-norm spectrum W
-  fused_forward<F, NZ, T>(v, lds, tw1, tw2, t, n0, m0);
+  fused_forward<F, NZ, T>(v, lds, tw1, TWL ? tw2s : tw2, t, n0, m0);
   fused_unpack<F, T>(v, bu, T(norm[j]), t);
   // opaque from here: otherwise the twiddles the unpack formed per register are
   // kept (spilled) across the product stage for the repack to reuse
@@ -404,7 +397,7 @@ __global__ __launch_bounds__(F::NT) void corr_fused_kernel(
   repack_mirror<F, MAP_MIRROR, T>(v, cM, t, [&](int) { return bu; });
   lds_barrier();  // every wave has left the forward exchange before the inverse writes LDS
   // 5. inverse transform, sigma, threshold
-  const double S = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
+  const double S = corr_ifft<F, T, 1, false, TWL>(v, lds, red, cols, tw1, TWL ? tw2s : tw2, t, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
   auto z = [&](int i) { return v[i]; };

@@ -469,9 +469,10 @@ __device__ __forceinline__ void corr_pre(cx<T>* v, double& acc, const uint32_t* 
 // PRE_BARRIER: a workgroup barrier before the first LDS write of the
 // exchange, for callers that loop over correlations (every wave has then
 // left the previous correlation's exchanges, whatever it did before).
-template <class F, typename T, int NACC = 1, bool PRE_BARRIER = false>
+// TW2S: tw2 is the LDS copy of the pass-2 table (fft3_tw2_stage).
+template <class F, typename T, int NACC = 1, bool PRE_BARRIER = false, bool TW2S = false>
 __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const uint32_t* cols,
-                                            const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2, int t,
+                                            const cx<T>* __restrict__ tw1, const cx<T>* tw2, int t,
                                             double acc, double acc2 = 0.0, double* S2 = nullptr) {
   fft3_pass1<F, +1>(v, tw1, cols);
   {
@@ -482,7 +483,8 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
       if ((t & 63) == 0) red[F::NW + (t >> 6)] = ws2;
     }
   }
-  const Pass2Anchors<F, T> an2 = fft3_pass2_load<F, T>(tw2, t);
+  Pass2Anchors<F, T> an2;
+  if constexpr (!TW2S) an2 = fft3_pass2_load<F, T>(tw2, t);
   if constexpr (PRE_BARRIER) lds_barrier();
   fft3_ex1_write<F, 0>(v, lds, cols);
   lds_barrier();
@@ -505,7 +507,11 @@ __device__ __forceinline__ double corr_ifft(cx<T>* v, T* lds, double* red, const
   lds_barrier();
   fft3_ex1_read<F, 1>(v, lds, t);
   lds_barrier();
-  fft3_pass2<F, +1>(v, an2);
+  if constexpr (TW2S) {
+    fft3_pass2_tab<F, +1>(v, tw2, t);
+  } else {
+    fft3_pass2<F, +1>(v, an2);
+  }
   fft3_ex2<F>(v, lds, t);
   fft3_pass3<F, +1>(v);
   return S;
@@ -653,11 +659,14 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0) {
   constexpr int M = F::M;
   constexpr double N = 2.0 * M;
+  constexpr bool TWL = tw2_in_lds<F>();
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
+  __shared__ cx<T> tw2s[TWL ? F::R2 * F::R3 : 1];
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
+  if constexpr (TWL) fft3_tw2_stage<F>(tw2s, tw2, t);
   const uint32_t s = __builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[row] : row0 + row);
   const uint32_t jg = j0 + j;  // template id in the whole bank
   const rsrc_t rW = make_rsrc(bank + uint64_t(j) * M, uint32_t(M) * uint32_t(sizeof(TW)));
@@ -670,7 +679,7 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
   // 32 points per thread: these kernels hold 4 waves per SIMD whatever their
   // register count below 128, so the early twiddle request is free
   corr_pre<F, MAP_MIRROR, G, T, TW, (F::P >= 32)>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
-  const double S = corr_ifft<F>(v, lds, red, cols, tw1, tw2, t, acc);
+  const double S = corr_ifft<F, T, 1, false, TWL>(v, lds, red, cols, tw1, TWL ? tw2s : tw2, t, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
   auto z = [&](int i) { return v[i]; };
@@ -693,8 +702,9 @@ __global__ __launch_bounds__(F::NT) void corr_kernel(
 
 // One correlation (template j of the launch's bank slice, spectrum row `row`)
 // by one workgroup of corr_loop_kernel: corr_kernel's stages, with the barrier
-// before the exchange that looping needs.  (corr_kernel keeps its own copy of
-// this sequence: sharing the function changed its register schedule.)
+// before the exchange that looping needs; tw2 is the workgroup's LDS copy of
+// the pass-2 twiddle table where tw2_in_lds<F>().  (corr_kernel keeps its own
+// copy of this sequence: sharing the function changed its register schedule.)
 template <typename T, typename TW, class F, bool DENSE, int G>
 __device__ __forceinline__ void corr_item(
     uint32_t j, uint32_t row, T* lds, double* red, const TW* __restrict__ bank, const cx<T>* __restrict__ yspec,
@@ -717,7 +727,7 @@ __device__ __forceinline__ void corr_item(
   // 32 points per thread: these kernels hold 4 waves per SIMD whatever their
   // register count below 128, so the early twiddle request is free
   corr_pre<F, MAP_MIRROR, G, T, TW, (F::P >= 32)>(v, acc, cols, rW, rY, 0u, tw_u, 1u, 0u, t);
-  const double S = corr_ifft<F, T, 1, true>(v, lds, red, cols, tw1, tw2, t, acc);
+  const double S = corr_ifft<F, T, 1, true, tw2_in_lds<F>()>(v, lds, red, cols, tw1, tw2, t, acc);
   const double rootS = sqrt(S);
   if (t == 0 && sigma_out) sigma_out[uint64_t(s) * k_total + jg] = rootS / N;
   auto z = [&](int i) { return v[i]; };
@@ -754,8 +764,11 @@ __global__ __launch_bounds__(F::NT) void corr_loop_kernel(
     tail_rec_t<T>* __restrict__ tails, unsigned long long* __restrict__ counter, uint64_t cap,
     unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off, double kappa_hi,
     T* __restrict__ rho_dense, uint32_t j0, uint32_t k_total, uint32_t row0, uint32_t n_items) {
+  constexpr bool TWL = tw2_in_lds<F>();
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
+  __shared__ cx<T> tw2s[TWL ? F::R2 * F::R3 : 1];
+  if constexpr (TWL) fft3_tw2_stage<F>(tw2s, tw2, int(threadIdx.x));
   for (uint32_t i = blockIdx.x; i < n_items; i += gridDim.x) {
     uint32_t j, row;
     if (!tile_map(i, K, n_rows, tile, j, row)) continue;
@@ -763,7 +776,7 @@ __global__ __launch_bounds__(F::NT) void corr_loop_kernel(
     // are formed where used, not hoisted out of the loop and kept (spilled) across it
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
-    corr_item<T, TW, F, DENSE, G>(j, row, lds, red, bank, yspec, seg_ids, tw_u, tw1, tw2, kappa, sigma_out,
+    corr_item<T, TW, F, DENSE, G>(j, row, lds, red, bank, yspec, seg_ids, tw_u, tw1, TWL ? tw2s : tw2, kappa, sigma_out,
                                         tails, counter, cap, proj, proj_off, kappa_hi, rho_dense, j0, k_total, row0, t);
   }
 }
@@ -1061,7 +1074,7 @@ template <typename T, typename TW, class F, bool DENSE, int G, int E>
 __device__ __forceinline__ void pair_body(T* lds, double* red, cx<T>* stash, const rsrc_t& rW, const rsrc_t& rA,
                                           const rsrc_t& rB, const uint32_t* seg, const uint32_t* prow_row, uint32_t jg,
                                           const cx<T>* __restrict__ tw_u, const cx<T>* __restrict__ tw1,
-                                          const cx<T>* __restrict__ tw2, double kappa, double kappa_hi,
+                                          const cx<T>* tw2, double kappa, double kappa_hi,
                                           double* __restrict__ sigma_out, uint32_t k_total, tail_rec_t<T>* __restrict__ tails,
                                           unsigned long long* __restrict__ counter, uint64_t cap,
                                           unsigned long long* __restrict__ proj, const uint64_t* __restrict__ proj_off,
@@ -1075,7 +1088,7 @@ __device__ __forceinline__ void pair_body(T* lds, double* red, cx<T>* stash, con
   for (int c = 0; c < F::C1; ++c) cols[c] = fft3_col<F, MAP_MIRROR>(t, c);
   pair_pre<F, G, E, T, TW>(v, acc_a, acc_b, cols, rW, rA, rB, tw_u, t, stash);
   double Sb = 0.0;
-  const double Sa = corr_ifft<F, T, 2>(v, lds, red, cols, tw1, tw2, t, acc_a, acc_b, &Sb);
+  const double Sa = corr_ifft<F, T, 2, false, tw2_in_lds<F>()>(v, lds, red, cols, tw1, tw2, t, acc_a, acc_b, &Sb);
   const double rootS[2] = {sqrt(Sa), sqrt(Sb)};
   if (E == 0 && t == 0 && sigma_out) {
     sigma_out[uint64_t(seg[0]) * k_total + jg] = rootS[0] / N;
@@ -1129,9 +1142,12 @@ __global__ __launch_bounds__(F::NT) void pair_kernel(
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[2 * F::NW];
   __shared__ cx<T> stash[F::R1];
+  constexpr bool TWL = tw2_in_lds<F>();
+  __shared__ cx<T> tw2s[TWL ? F::R2 * F::R3 : 1];
   const int t = threadIdx.x;
   uint32_t j, row;
   if (!tile_map(blockIdx.x, K, n_rows, tile, j, row)) return;
+  if constexpr (TWL) fft3_tw2_stage<F>(tw2s, tw2, t);
   const uint32_t ra = row & ~1u, rb = ra + 1u;
   const uint32_t seg[2] = {uint32_t(__builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[ra] : row0 + ra)),
                            uint32_t(__builtin_amdgcn_readfirstlane(seg_ids ? seg_ids[rb] : row0 + rb))};
@@ -1141,10 +1157,10 @@ __global__ __launch_bounds__(F::NT) void pair_kernel(
   const rsrc_t rA = make_rsrc(yspec + uint64_t(ra) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   const rsrc_t rB = make_rsrc(yspec + uint64_t(rb) * M, uint32_t(M) * uint32_t(sizeof(cx<T>)));
   if (row & 1u)
-    pair_body<T, TW, F, DENSE, G, 1>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, tw2, kappa,
+    pair_body<T, TW, F, DENSE, G, 1>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, TWL ? tw2s : tw2, kappa,
                                      kappa_hi, sigma_out, k_total, tails, counter, cap, proj, proj_off, rho_dense, t);
   else
-    pair_body<T, TW, F, DENSE, G, 0>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, tw2, kappa,
+    pair_body<T, TW, F, DENSE, G, 0>(lds, red, stash, rW, rA, rB, seg, prow_row, jg, tw_u, tw1, TWL ? tw2s : tw2, kappa,
                                      kappa_hi, sigma_out, k_total, tails, counter, cap, proj, proj_off, rho_dense, t);
 }
 

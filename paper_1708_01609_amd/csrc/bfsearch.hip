@@ -515,11 +515,14 @@ bfs_status tune_size(bfs_plan* p, SizePlan& sp) {
       if (r == 1 || (r > 1 && ms < ms_min)) ms_min = ms;
     }
     sp.tile_us[i] = ms_min * 1000.f / float(Kt * TUNE_SEGS);
-    if (i == 0 || ms_min < best_tile_ms) {
-      sp.tile = TILES[i];
-      best_tile_ms = ms_min;
-    }
+    if (i == 0 || ms_min < best_tile_ms) best_tile_ms = ms_min;
   }
+  // The largest tile within 2 % of the fastest: timed on a slice of the bank,
+  // tiles that differ by noise there differ at full size, where each pass of a
+  // smaller tile reads the whole bank from HBM again (a 2^17 bank of 65,536
+  // chirps is 32 GiB).
+  for (int i = 0; i < N_TILES && st == BFS_OK; ++i)
+    if (sp.tile_us[i] * float(Kt * TUNE_SEGS) <= 1.02f * best_tile_ms * 1000.f) sp.tile = TILES[i];
   if (y) (void)hipFree(y);
   if (tails) (void)hipFree(tails);
   if (counter) (void)hipFree(counter);

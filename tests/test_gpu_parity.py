@@ -446,8 +446,12 @@ def test_autotuned_plan_reports_timings_and_stays_correct(bfs):
             print("autotuned", info)
             assert len(info["tuned_us"]) == info["n_candidates"] and all(t > 0 for t in info["tuned_us"])
             assert info["tuned_us"][info["candidate"]] == min(info["tuned_us"])
-            assert all(v > 0 for v in info["tile_us"].values())
-            assert info["tile_us"][info["tile"]] == min(info["tile_us"].values())
+            tus = info["tile_us"]
+            assert all(v > 0 for v in tus.values())
+            # the largest tile within 2 % of the fastest (a little slack for float rounding)
+            best = min(tus.values())
+            assert tus[info["tile"]] <= 1.02 * best * (1 + 1e-5)
+            assert all(us > 1.02 * best * (1 - 1e-5) for t, us in tus.items() if t > info["tile"])
 
 
 @pytest.mark.parametrize("prec", ["f32-w16f", "f32-w16b"], ids=["fp16", "bf16"])
