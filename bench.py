@@ -32,12 +32,12 @@ if ROOT not in sys.path:
 PEAK_FP32_VECTOR = 157.3e12   # MI355X published FP32 vector peak, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 
-# HBM bytes per corr_kernel launch on the C2 workload, from rocprofv3 FETCH_SIZE (x2, the
-# factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid only
-# for the kernel sources and build flags they were taken on
-# (profiles/corr_kernel_C2_N65536_K8192_hbm.md).
+# HBM bytes per correlation-kernel launch on the C2 workload, from rocprofv3 FETCH_SIZE (x2,
+# the factor a plain copy kernel of known size reads on this gfx950) + WRITE_SIZE (x1); valid
+# only for the kernel sources and build flags they were taken on
+# (profiles/corr_loop_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "108883633739917c": {"f32": 2.2073e+09, "f32-w16f": 1.0893e+09, "f32-w16b": 1.0890e+09, "f32 fused": 6.98e+06},
+    "9152f1b9b9c29599": {"f32": 2.1963e+09, "f32-w16f": 1.0867e+09, "f32-w16b": 1.0884e+09, "f32 fused": 7.0088e+06},
 }
 
 
