@@ -217,29 +217,42 @@ __global__ __launch_bounds__(256) void rfft_unpack_kernel(const cx<T>* Z, TW* ou
 
 // Join of a transform split A ways by fwd_fft_kernel (zs = A): with the
 // sub-transforms T_r[k2] = sum_m z_{r + A m} exp(-2 pi i m k2 / B), B = M / A,
-//   Z_{k2 + B k1} = sum_{r<A} (T_r[k2] exp(-2 pi i r k2 / M)) exp(-2 pi i r k1 / A).
-// One thread per k2 of one segment (blockIdx.y): A loads, the twiddles from
-// tw_u (exp(+2 pi i k / N), k < M: exp(-2 pi i m / M) is conj(tw_u[2m]) or,
-// past M, -conj(tw_u[2m - M])), a length-A DFT, A stores; in and out are
-// [segments][M] (in: A rows of B).
+//   Z_k = sum_{r<A} T_r[k mod B] exp(-2 pi i r k / M)
+// (the twiddle of sub-transform r and the length-A DFT in one factor).  One
+// thread per output k of one segment (blockIdx.y), so a segment's join spreads
+// over M / 256 workgroups: A loads of T (coalesced over consecutive k), the
+// twiddles from tw_u (exp(+2 pi i j / N), j < M: exp(-2 pi i m / M) is
+// conj(tw_u[2m mod N]) or, past M, -conj(tw_u[2m mod N - M])), FMA sums.  M is a
+// power of two; in and out are [segments][M] (in: A rows of B).
 template <typename T, int A>
 __global__ __launch_bounds__(256) void fft_join_kernel(const cx<T>* __restrict__ in, cx<T>* __restrict__ out,
                                                        const cx<T>* __restrict__ tw_u, uint32_t M) {
   const uint32_t B = M / A;
-  const uint32_t k2 = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k2 >= B) return;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
   const uint64_t base = uint64_t(blockIdx.y) * M;
-  cx<T> v[A];
+  const cx<T>* row = in + base + (k & (B - 1u));
+  const uint32_t mask = 2u * M - 1u;
+  // four partial sums (r mod 4): shorter FMA chains, smaller rounding growth
+  constexpr int NA = A >= 4 ? 4 : A;
+  cx<T> acc[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) acc[q] = {T(0), T(0)};
 #pragma unroll
   for (int r = 0; r < A; ++r) {
-    const cx<T> a = in[base + uint64_t(r) * B + k2];
-    const uint32_t e = uint32_t((2ull * r * k2) % (2ull * M));  // 2 m mod N, m = r k2 mod M
-    const cx<T> w = e < M ? conjg(tw_u[e]) : cx<T>{-tw_u[e - M].x, tw_u[e - M].y};
-    v[r] = cmul(a, w);
+    const cx<T> a = row[uint64_t(r) * B];
+    const uint32_t e = (2u * uint32_t(r) * k) & mask;  // 2 (r k mod M)
+    const cx<T> t = tw_u[e < M ? e : e - M];
+    // w = exp(-2 pi i r k / M) = (t.x, -t.y), or (-t.x, t.y) past M
+    const T wx = e < M ? t.x : -t.x, wy = e < M ? -t.y : t.y;
+    cx<T>& c = acc[r % NA];
+    c.x = fmad<T>(a.x, wx, fmad<T>(-a.y, wy, c.x));
+    c.y = fmad<T>(a.x, wy, fmad<T>(a.y, wx, c.y));
   }
-  dft<A, -1, T>(v);
+  cx<T> z = acc[0];
 #pragma unroll
-  for (int k1 = 0; k1 < A; ++k1) out[base + k2 + uint64_t(B) * k1] = v[k1];
+  for (int q = 1; q < NA; ++q) z = cadd(z, acc[q]);
+  out[base + k] = z;
 }
 
 // Packed storage -> FP64 interleaved [rows][M+1][2] in natural bin order (diagnostics).

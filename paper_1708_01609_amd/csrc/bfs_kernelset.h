@@ -254,7 +254,7 @@ struct Impl {
   static constexpr int JOIN_A = (!SPLIT && M >= 2048 && M <= 32768) ? M / 1024 : 0;
   static hipError_t join(uint32_t count, hipStream_t st, const void* in, void* out, const void* tw_u) {
     if constexpr (JOIN_A > 1) {
-      const dim3 grid((1024 + 255) / 256, count);
+      const dim3 grid(uint32_t(M) / 256, count);
       hipLaunchKernelGGL((fft_join_kernel<T, JOIN_A>), grid, dim3(256), 0, st, static_cast<const cx<T>*>(in),
                          static_cast<cx<T>*>(out), static_cast<const cx<T>*>(tw_u), uint32_t(M));
       return hipGetLastError();

@@ -92,6 +92,36 @@ __global__ __launch_bounds__(256) void coinc_kernel(const unsigned long long* __
   if (idx < cap) out[idx] = coinc_rec{p, uint32_t(n), ja, jb, sa, sb};
 }
 
+// A finished job's counters and the head of each result list, copied into
+// pinned host memory by the job's own stream right after its kernels, while
+// the CUs are free.  (A copy queued from the host later runs as a blit kernel
+// and, once the next job's persistent correlation kernel holds every CU,
+// waits for that whole kernel.)  counter[0..2] counts tails, projection
+// entries and coincidences; list i gets min(counter[i], cap) entries of
+// `words` 8-byte words (dst null: nothing).
+struct PublishList {
+  const uint2* src;
+  uint2* dst;
+  uint64_t cap;
+  uint32_t words;
+};
+
+__global__ __launch_bounds__(256) void publish_kernel(const unsigned long long* __restrict__ counter,
+                                                      unsigned long long* __restrict__ count_dst, PublishList l0,
+                                                      PublishList l1, PublishList l2) {
+  if (blockIdx.x == 0 && threadIdx.x < 3) count_dst[threadIdx.x] = counter[threadIdx.x];
+  const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+  const uint64_t t0 = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  auto copy = [&](const PublishList& l, unsigned long long cnt) {
+    if (!l.dst) return;
+    const uint64_t n = (uint64_t(cnt) < l.cap ? uint64_t(cnt) : l.cap) * l.words;
+    for (uint64_t i = t0; i < n; i += stride) l.dst[i] = l.src[i];
+  };
+  copy(l0, counter[0]);
+  copy(l1, counter[1]);
+  copy(l2, counter[2]);
+}
+
 // FP64 energy sum_m w[m]^2 of each grid chirp (the unit-norm factor of the
 // fused kernel is 1 / sqrt of it, as the resident bank's unpack applies).
 // One workgroup per template; the samples are the chirp_sample values.

@@ -27,6 +27,11 @@ static_assert(sizeof(coinc_rec) == sizeof(bfs_coinc), "coincidence record layout
 
 namespace {
 
+// Result-list heads a job publishes to pinned host memory at its end (tails:
+// up to the count sorted on the host; projection entries; coincidences).
+constexpr uint64_t PUB_TAILS = 1u << 15;
+constexpr uint64_t PUB_PROJ = 1u << 17;
+constexpr uint64_t PUB_COINC = 1u << 15;
 constexpr int N_TILES = 5;
 constexpr uint32_t TILES[N_TILES] = {1, 2, 4, 8, 16};
 
@@ -131,17 +136,26 @@ struct JobBuffers {
   unsigned long long* proj = nullptr;        // projection keys [sum of segment lengths]
   unsigned long long* plist = nullptr;       // compacted (index, key) pairs
   coinc_rec* clist = nullptr;                // coincidences of detector pairs
-  unsigned long long* count_host = nullptr;  // pinned copy of the counters (tails, projection entries)
+  unsigned long long* count_host = nullptr;  // pinned: the job's published counters (tails, projection, coincidences)
   void* tails_host = nullptr;                // pinned staging of fetched tails (the plan's records)
   uint64_t tails_host_cap = 0;
+  // pinned, written by publish_kernel at the job's end: the first pub_* entries of each
+  // list (never reallocated: captured graphs hold these addresses)
+  void* pub_tails = nullptr;
+  unsigned long long* pub_proj = nullptr;
+  coinc_rec* pub_coinc = nullptr;
+  uint64_t pub_tails_cap = 0, pub_proj_cap = 0, pub_coinc_cap = 0;
+  void* dev_count_host = nullptr;  // device addresses of count_host and the pub_* buffers
+  void* dev_pub_tails = nullptr;
+  void* dev_pub_proj = nullptr;
+  void* dev_pub_coinc = nullptr;
   void* sorted = nullptr;  // device: sorted tail records [sort_cap], then the sort's work area
   uint64_t sort_cap = 0;
   uint64_t sort_bytes = 0;
   // [0] job queued, [1]/[2] around the correlation kernels, [3] job done
-  // after the projection compaction, [4] segment transforms done (orders the
-  // correlation stream after them).  done = the event that completes the
-  // job: 3 when the compaction follows the kernels, else 2 (each record on
-  // the correlation stream costs a few microseconds between kernels).
+  // after the publication of its results, [4] segment transforms done (orders
+  // the correlation stream after them).  done = the event that completes the
+  // job: 3, or 2 for dense correlations (nothing published).
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   int done = 3;
   uint64_t bytes = 0;
@@ -263,6 +277,9 @@ void free_job_buffers(JobBuffers* b) {
     if (q) (void)hipFree(q);
   if (b->meta_host) (void)hipHostFree(b->meta_host);
   if (b->count_host) (void)hipHostFree(b->count_host);
+  if (b->pub_tails) (void)hipHostFree(b->pub_tails);
+  if (b->pub_proj) (void)hipHostFree(b->pub_proj);
+  if (b->pub_coinc) (void)hipHostFree(b->pub_coinc);
   if (b->tails_host) (void)hipHostFree(b->tails_host);
   if (b->sorted) (void)hipFree(b->sorted);
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -757,6 +774,28 @@ bfs_status get_job_buffers(bfs_plan* p, const JobNeed& need, JobBuffers** out) {
     (void)hipGetLastError();
     st = BFS_ERR_OUT_OF_MEMORY;
   }
+  if (st == BFS_OK) {
+    b->pub_tails_cap = std::min<uint64_t>(p->cap, PUB_TAILS);
+    b->pub_proj_cap = std::min<uint64_t>(c.proj, PUB_PROJ);
+    b->pub_coinc_cap = std::min<uint64_t>(c.coinc, PUB_COINC);
+    if ((b->pub_tails_cap && hipHostMalloc(&b->pub_tails, b->pub_tails_cap * p->rec_bytes, hipHostMallocDefault) !=
+                                 hipSuccess) ||
+        (b->pub_proj_cap && hipHostMalloc(reinterpret_cast<void**>(&b->pub_proj), b->pub_proj_cap * 16,
+                                          hipHostMallocDefault) != hipSuccess) ||
+        (b->pub_coinc_cap && hipHostMalloc(reinterpret_cast<void**>(&b->pub_coinc),
+                                           b->pub_coinc_cap * sizeof(coinc_rec), hipHostMallocDefault) != hipSuccess)) {
+      (void)hipGetLastError();
+      st = BFS_ERR_OUT_OF_MEMORY;
+    }
+  }
+  if (st == BFS_OK) {
+    auto dev = [](void* h, void** d) { return !h || hipHostGetDevicePointer(d, h, 0) == hipSuccess; };
+    if (!dev(b->count_host, &b->dev_count_host) || !dev(b->pub_tails, &b->dev_pub_tails) ||
+        !dev(b->pub_proj, &b->dev_pub_proj) || !dev(b->pub_coinc, &b->dev_pub_coinc)) {
+      (void)hipGetLastError();
+      st = BFS_ERR_HIP;
+    }
+  }
   for (int i = 0; i < 4 && st == BFS_OK; ++i)
     if (hipEventCreate(&b->ev[i]) != hipSuccess) st = BFS_ERR_HIP;
   if (st == BFS_OK && hipEventCreateWithFlags(&b->ev[4], hipEventDisableTiming) != hipSuccess) st = BFS_ERR_HIP;
@@ -977,11 +1016,29 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
 }
 
 // The whole job on one stream (graph capture, dense correlation).
+// The job's counters and list heads to pinned host memory, on st after its
+// kernels (publish_kernel).
+bfs_status enqueue_publish(bfs_plan* p, JobBuffers* b, hipStream_t st) {
+  const uint32_t tail_words = uint32_t(p->rec_bytes / 8);
+  const PublishList lt{static_cast<const uint2*>(b->tails), static_cast<uint2*>(b->dev_pub_tails), b->pub_tails_cap,
+                       tail_words};
+  const PublishList lp{reinterpret_cast<const uint2*>(b->plist), static_cast<uint2*>(b->dev_pub_proj), b->pub_proj_cap,
+                       2u};
+  const PublishList lc{reinterpret_cast<const uint2*>(b->clist), static_cast<uint2*>(b->dev_pub_coinc),
+                       b->pub_coinc_cap, uint32_t(sizeof(coinc_rec) / 8)};
+  hipLaunchKernelGGL(publish_kernel, dim3(16), dim3(256), 0, st, b->counter,
+                     static_cast<unsigned long long*>(b->dev_count_host), lt, lp, lc);
+  HIP_TRY(hipGetLastError());
+  return BFS_OK;
+}
+
 bfs_status enqueue_body(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
                         hipStream_t st, bool with_events, uint32_t first = 0, uint32_t count = 0) {
-  const bfs_status rs = enqueue_prep(p, b, L, dense, st);
+  bfs_status rs = enqueue_prep(p, b, L, dense, st);
   if (rs != BFS_OK) return rs;
-  return enqueue_corr(p, b, L, dense, rho, sigma, st, with_events, first, count);
+  rs = enqueue_corr(p, b, L, dense, rho, sigma, st, with_events, first, count);
+  if (rs != BFS_OK || dense) return rs;
+  return enqueue_publish(p, b, st);
 }
 
 // The correlation stream paired with the caller's stream st (created on first
@@ -1076,19 +1133,12 @@ bfs_status queue_job(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, vo
     *done_stream = cs;
     rs = enqueue_corr(p, b, L, false, nullptr, nullptr, cs, true);
     if (rs != BFS_OK) return rs;
+    rs = enqueue_publish(p, b, cs);
+    if (rs != BFS_OK) return rs;
   }
-  b->done = (p->project && !dense) ? 3 : 2;
+  b->done = dense ? 2 : 3;
   if (b->done == 3) HIP_TRY(hipEventRecord(b->ev[3], *done_stream));
   return BFS_OK;
-}
-
-// Copy the job's two counters (tails, projection entries) to the pinned host
-// copy; the job has finished.
-hipError_t read_counters(bfs_plan* p, JobBuffers* b) {
-  hipError_t e = hipMemcpyAsync(b->count_host, b->counter, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                p->copy_stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(p->copy_stream);
-  return e;
 }
 
 // Fetches of at least DEVICE_SORT_MIN tails are ordered on the device.
@@ -1190,9 +1240,17 @@ bfs_status sorted_tails(bfs_job* j, const R** recs, uint64_t* on_dev_out, unsign
   bfs_plan* p = j->plan;
   JobBuffers* b = j->buf;
   HIP_TRY(hipEventSynchronize(b->ev[b->done]));
-  HIP_TRY(read_counters(p, b));
-  const unsigned long long count = *b->count_host;
+  const unsigned long long count = b->count_host[0];  // published at the job's end
   const uint64_t on_dev = std::min<uint64_t>(count, p->cap);
+  if (on_dev < DEVICE_SORT_MIN && on_dev <= b->pub_tails_cap) {
+    // the records are in host memory already: sort them where they are
+    R* pub = static_cast<R*>(b->pub_tails);
+    sort_tails(pub, on_dev);
+    *recs = pub;
+    *on_dev_out = on_dev;
+    *count_out = count;
+    return BFS_OK;
+  }
   if (on_dev > b->tails_host_cap) {
     if (b->tails_host) (void)hipHostFree(b->tails_host);
     b->tails_host = nullptr;
@@ -1564,10 +1622,11 @@ bfs_status bfsearch_fetch_projection(bfs_job* j, bfs_peak* out_host, uint64_t ca
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(hipEventSynchronize(b->ev[b->done]));
-  HIP_TRY(read_counters(p, b));
   const unsigned long long count = b->count_host[1];  // <= the number of lags, the list's size
   std::vector<unsigned long long> list(2 * count);
-  if (count) {
+  if (count && count <= b->pub_proj_cap) {
+    std::memcpy(list.data(), b->pub_proj, 2 * count * sizeof(unsigned long long));
+  } else if (count) {
     HIP_TRY(hipMemcpyAsync(list.data(), b->plist, 2 * count * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                            p->copy_stream));
     HIP_TRY(hipStreamSynchronize(p->copy_stream));
@@ -1607,10 +1666,11 @@ bfs_status bfsearch_fetch_coincidences(bfs_job* j, bfs_coinc* out_host, uint64_t
   JobBuffers* b = j->buf;
   if (hipSetDevice(p->device) != hipSuccess) return BFS_ERR_HIP;
   HIP_TRY(hipEventSynchronize(b->ev[b->done]));
-  HIP_TRY(read_counters(p, b));
   const unsigned long long count = b->count_host[2];  // <= the pairs' lags, the list's size
   std::vector<coinc_rec> list(count);
-  if (count) {
+  if (count && count <= b->pub_coinc_cap) {
+    std::memcpy(list.data(), b->pub_coinc, count * sizeof(coinc_rec));
+  } else if (count) {
     HIP_TRY(hipMemcpyAsync(list.data(), b->clist, count * sizeof(coinc_rec), hipMemcpyDeviceToHost, p->copy_stream));
     HIP_TRY(hipStreamSynchronize(p->copy_stream));
   }

@@ -571,7 +571,11 @@ def test_band_threshold_matches_oracle(bfs):
     only = (g.keys() - o.keys()) | (o.keys() - g.keys())
     assert all(near_edge(j, n) for j, n in only)
     assert all(abs(g[k] - o[k]) <= TOL["f32"] * tol_scale(sig[k[0]], floor[k[0]]) for k in g.keys() & o.keys())
-    assert all(kappa < abs(r) / sig[j] < kappa_hi + tol[j] for (j, n), r in g.items())
+    # every GPU tail inside the band, up to the tolerance at either edge (a GPU decision at
+    # kappa sigma in FP32 can fall a rounding error on the other side of the oracle's)
+    bad = [(j, n, abs(r) / sig[j], tol[j]) for (j, n), r in g.items()
+           if not (kappa - tol[j] < abs(r) / sig[j] < kappa_hi + tol[j])]
+    assert not bad, bad[:10]
     print(f"band: {total} GPU tails, {len(o)} oracle, {len(only)} differ within the band edges")
     assert len(g.keys() & o.keys()) > 1000 and len(only) <= len(o) // 100
 
