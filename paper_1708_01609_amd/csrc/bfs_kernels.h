@@ -47,6 +47,8 @@ __device__ __forceinline__ double chirp_sample(int m, int len, double f0, double
 // ways: workgroup b transforms the sub-sequence z_{r + zs m}, m < F::M, of
 // segment b / zs (r = b mod zs), for fft_join_kernel to combine.  Without split, workgroup b transforms item b.  With split, workgroup b = 2 item + h transforms the
 // samples z_{2n+h}, n < F::M (h = 0 even, 1 odd).  Spectra go to out + b F::M.
+// zero (may be null): three counters the first workgroup clears (a job's tail
+// counters, so the job needs no launch of its own for them).
 // The chirp source writes the FP64 sum of x^2 over the samples it made to
 // energy[b] (the unpack turns it into the unit-norm scale); SRC_CHIRP_SYM
 // synthesises the chirp plus its time reversal, x[m] + x[L-1-m].
@@ -56,11 +58,13 @@ __global__ __launch_bounds__(F::NT) void fwd_fft_kernel(
     const double* __restrict__ f0, const double* __restrict__ fdot, const uint32_t* __restrict__ len,
     double fs, int taper, uint32_t first,
     const cx<T>* __restrict__ tw1, const cx<T>* __restrict__ tw2,
-    cx<T>* __restrict__ out, double* __restrict__ energy, int split, uint32_t zs) {
+    cx<T>* __restrict__ out, double* __restrict__ energy, int split, uint32_t zs,
+    unsigned long long* __restrict__ zero) {
   __shared__ T lds[F::LDS_ELEMS];
   __shared__ double red[F::NW];
   const int t = threadIdx.x;
   const uint32_t b = blockIdx.x;
+  if (zero && b == 0 && t < 3) zero[t] = 0ull;
   const uint32_t item = split ? (b >> 1) : (zs > 1 ? b / zs : b);
   const uint32_t half = split ? (b & 1u) : (zs > 1 ? b % zs : 0u);
   const uint32_t cs = split ? 2u : (zs > 1 ? zs : 1u);  // stride of z between the transform's samples

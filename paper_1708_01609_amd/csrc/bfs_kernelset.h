@@ -38,6 +38,7 @@ struct FwdArgs {
   void* out;
   double* energy;
   uint32_t zs;  // > 1: segments' transforms split zs ways (sub-sequence b mod zs of segment b / zs)
+  unsigned long long* zero;  // not null: three counters the launch's first workgroup clears
 };
 
 struct CorrArgs {
@@ -111,16 +112,16 @@ struct Impl {
     auto* out = static_cast<cx<T>*>(a.out);
     if (src == SRC_SAMPLES)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_SAMPLES>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs, a.zero);
     else if (src == SRC_CHIRP)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs, a.zero);
     else if (src == SRC_CHIRP_SYM)
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_CHIRP_SYM>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs, a.zero);
     else
       hipLaunchKernelGGL((fwd_fft_kernel<T, F, SRC_EXPLICIT>), grid, block, 0, st, a.src, a.src_stride, a.src_len,
-                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs);
+                         a.seg_ptr, a.f0, a.fdot, a.len, a.fs, a.taper, a.first, t1, t2, out, a.energy, SPLIT, a.zs, a.zero);
     return hipGetLastError();
   }
   static hipError_t unpack_bank(uint32_t batch, hipStream_t st, const void* Z, void* out, const double* energy,

@@ -418,9 +418,11 @@ bfs_status set_sub_tables(SizePlan& sp) {
 // the others as one workgroup per segment (two halves at the split length)
 // and the unpack.  z: scratch of the same size as y (split and joined paths).
 bfs_status queue_segment_fft(const SizePlan& sp, uint32_t count, const uint64_t* seg_ptr, const void* src,
-                             uint64_t src_stride, void* y, void* z, hipStream_t st) {
+                             uint64_t src_stride, void* y, void* z, hipStream_t st,
+                             unsigned long long* zero = nullptr) {
   const KernelSet& ks = *sp.ks;
   FwdArgs a{};
+  a.zero = zero;
   a.seg_ptr = seg_ptr;
   a.src = src;
   a.src_stride = src_stride;
@@ -910,13 +912,12 @@ void stage_table(const bfs_plan* p, const void* y_dev, const uint64_t* offs, con
   }
 }
 
-// Queue the first part of a job on st: counter reset, table upload, the
-// segment transforms of every group.
+// Queue the first part of a job on st: the projection-key reset, the table
+// upload, the segment transforms of every group (the first also clears the
+// job's counters).
 bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, hipStream_t st) {
   const uint32_t S = uint32_t(L.seg_len.size());
   const bool project = p->project && !dense;
-  hipLaunchKernelGGL(fill_u64_kernel, dim3(1), dim3(64), 0, st, b->counter, uint64_t(3), 0ull);
-  HIP_TRY(hipGetLastError());
   if (project) {
     const uint64_t n = L.need.proj;
     hipLaunchKernelGGL(fill_u64_kernel, dim3(uint32_t((n + 255) / 256)), dim3(256), 0, st, b->proj, n, 0ull);
@@ -925,10 +926,14 @@ bfs_status enqueue_prep(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   HIP_TRY(hipMemcpyAsync(b->meta, b->meta_host, table_bytes(S), hipMemcpyHostToDevice, st));
   const auto* dptr = static_cast<const uint64_t*>(b->meta);
   char* ybase = static_cast<char*>(b->y);
+  // the first group's transform clears the job's counters (every correlation
+  // kernel runs after all of the job's transforms)
+  unsigned long long* zero = b->counter;
   for (const Group& g : L.groups) {
     const KernelSet& ks = *g.sp->ks;
     void* yg = ybase + g.y_off;
-    const bfs_status rs = queue_segment_fft(*g.sp, g.count, dptr + g.first, nullptr, 0, yg, b->z, st);
+    const bfs_status rs = queue_segment_fft(*g.sp, g.count, dptr + g.first, nullptr, 0, yg, b->z, st, zero);
+    zero = nullptr;
     if (rs != BFS_OK) return rs;
     if (p->fused) HIP_TRY(ks.permute_y(g.count, st, yg, ybase + g.yf_off));
   }
@@ -1185,7 +1190,9 @@ bool ensure_sort(bfs_plan* p, JobBuffers* b, uint64_t n) {
 
 // Tails in (segment, template_id, lag) order.  The device writes them in
 // whatever order the atomics hand out slots; sorting makes the result
-// deterministic.  LSD radix sort (16-bit digits) of the packed key
+// deterministic.  LSD radix sort (8-bit digits: 256 counters per pass, where
+// 16-bit digits spend most of a small sort on clearing and scanning 65,536;
+// passes whose digit is the same for every key are skipped) of the packed key
 // segment << 48 | template_id << 17 | lag when every field fits (segments
 // < 2^16, templates < 2^31, lags < 2^17), else a comparison sort.
 template <typename R>
@@ -1208,10 +1215,10 @@ void sort_tails(R* t, uint64_t n) {
     key[i] = (uint64_t(t[i].segment) << 48) | (uint64_t(t[i].template_id) << 17) | t[i].lag;
     idx[i] = uint32_t(i);
   }
-  std::vector<uint64_t> count(1u << 16);
-  for (int shift = 0; shift < 64; shift += 16) {
+  std::vector<uint64_t> count(1u << 8);
+  for (int shift = 0; shift < 64; shift += 8) {
     std::fill(count.begin(), count.end(), 0);
-    for (uint64_t i = 0; i < n; ++i) ++count[(key[i] >> shift) & 0xffffu];
+    for (uint64_t i = 0; i < n; ++i) ++count[(key[i] >> shift) & 0xffu];
     if (*std::max_element(count.begin(), count.end()) == n) continue;  // one digit value: already ordered
     uint64_t sum = 0;
     for (auto& c : count) {
@@ -1220,7 +1227,7 @@ void sort_tails(R* t, uint64_t n) {
       sum += v;
     }
     for (uint64_t i = 0; i < n; ++i) {
-      const uint64_t d = (key[i] >> shift) & 0xffffu;
+      const uint64_t d = (key[i] >> shift) & 0xffu;
       key2[count[d]] = key[i];
       idx2[count[d]++] = idx[i];
     }
