@@ -205,6 +205,32 @@ def run_plan(bfs, torch, w, y_dev, precision, steps, warmup, depth=2, project=Fa
     return wall, build_s, corr_ms, lat_ms, n_tails, info
 
 
+def library_c2r_context(torch, n, batch, kernel_rate, reps=10):
+    """The platform FFT library's batched complex-to-real inverse transform of length n
+    (torch.fft.irfft, which runs hipFFT / rocFFT on ROCm), timed with events over `reps`
+    calls after three warm-up calls.  Context for the paper's efficiency figure, which states
+    its whole correlation pipeline as about 65 % of clFFT's transform rate alone (Sec. 4);
+    here the ratio is the correlation kernel's rate over the library's bare C2R rate at
+    the same length and batch.  A measurement beside the product path, never part of it."""
+    x = torch.randn(batch, n // 2 + 1, dtype=torch.complex64, device="cuda:0")
+    out = torch.empty(batch, n, dtype=torch.float32, device="cuda:0")
+    for _ in range(3):
+        torch.fft.irfft(x, n=n, out=out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.fft.irfft(x, n=n, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    rate = batch / (ms * 1e-3)
+    del x, out
+    torch.cuda.empty_cache()
+    return {"library": "torch.fft.irfft (hipFFT / rocFFT), complex64 -> float32", "n": n, "batch": batch,
+            "ms_per_batch": ms, "transforms_per_s": rate, "correlation_kernel_over_library_c2r": kernel_rate / rate}
+
+
 def run_pairs(bfs, torch, w, args):
     """Detector pairs: the C2 segment (channel 0) and a second, independent channel of the same
     shape correlated as one pair (both channels through one complex inverse transform per
@@ -584,6 +610,7 @@ def main():
         line["band_threshold"] = {"kappa": 3.0, "kappa_hi": 3.5, "value": args.steps * k / wallb,
                                   "kernel_rate": k / (np.mean(corrb) * 1e-3), "tails_per_step": n_band}
         line["detector_pairs"] = run_pairs(bfs, torch, w, args)
+        line["library_c2r_context"] = library_c2r_context(torch, w.n, k, k / corr_avg_s)
     if forms and args.precision == "f32":
         # fused synthesis on the C2 workload: the same search with no resident bank
         wallf, buildf, corrf, _, _, infof = run_plan(bfs, torch, w, y_dev, "f32", args.steps, args.warmup,
