@@ -511,6 +511,43 @@ def test_workgroup_order_tiles_cover_every_correlation_once(bfs):
                   lambda s, j: oracle.correlate_fft(ys[s].astype(np.float64), tw[j]))
 
 
+def test_persistent_kernel_with_tiles_and_a_ragged_bank(bfs):
+    # the looping 2^16 kernels walk the tile order with a stride of their grid: with
+    # K = 13 (three of the eight XCD residues hold one template fewer, so their workgroups
+    # run out of items first) and S = 5 segments, every tile gives the same sigma and
+    # tails as tile 1, bitwise, and those match the oracle
+    n = 1 << 16
+    rng = np.random.default_rng(16)
+    ys = (rng.standard_normal((5, n)) + 0.1).astype(np.float32)
+    temps = rng.standard_normal((13, 4096))
+    kappa = 4.0
+    with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32") as plan:
+        count = plan.kernel_info()["n_candidates"]
+    looping = []
+    for c in range(1, count + 1):
+        with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32", candidate=c) as plan:
+            if plan.kernel_info()["loop"]:
+                looping.append(c)
+    assert looping, "no looping candidate at 2^16"
+    tw = [x.astype(np.float32).astype(np.float64) for x in temps]
+    out = oracle.search([y.astype(np.float64) for y in ys], tw, kappa)
+    for c in looping:
+        res = {}
+        for t in (1, 2, 5):
+            with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32", candidate=c, tile=t) as plan:
+                info = plan.kernel_info()
+                assert info["loop"] and info["tile"] == t
+                with plan.filter(_dev(ys, np.float32)) as job:
+                    res[t] = (job.fetch_tails()[0], job.fetch_sigma())
+        for t, (tl, sg) in res.items():
+            assert np.array_equal(tl, res[1][0]) and np.array_equal(sg, res[1][1]), (c, t)
+        assert np.max(np.abs(res[1][1] - out["sigma"]) / out["sigma"]) <= TOL["f32"]
+        common, _ = compare_tails(res[1][0], out["tails"], out["sigma"], kappa, TOL["f32"],
+                                  lambda s, j: oracle.correlate_fft(ys[s].astype(np.float64), tw[j]))
+        print(f"looping candidate {c}: {len(res[1][0])} tails, {common} common with the oracle")
+        assert common > 0
+
+
 def test_time_symmetric_bank_spectra_and_c1_search(bfs):
     # time-symmetric templates (chirp plus its reversal) synthesised on the device: spectra at
     # every plan length against the oracle, and the C1 search in FP64 against the oracle
