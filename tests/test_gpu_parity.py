@@ -548,6 +548,38 @@ def test_persistent_kernel_with_tiles_and_a_ragged_bank(bfs):
         assert common > 0
 
 
+def test_split_kernel_with_tiles_and_a_ragged_bank(bfs):
+    # the 2^17 correlations run as two halves with the even one waiting in scratch memory:
+    # every candidate and tile over K = 13 templates and S = 3 segments gives tile 1's sigma
+    # and tails bitwise, and those match the oracle
+    n = 1 << 17
+    rng = np.random.default_rng(17)
+    ys = (rng.standard_normal((3, n)) + 0.1).astype(np.float32)
+    temps = rng.standard_normal((13, 4096))
+    kappa = 4.0
+    with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32") as plan:
+        count = plan.kernel_info()["n_candidates"]
+        assert plan.kernel_info()["split"]
+    tw = [x.astype(np.float32).astype(np.float64) for x in temps]
+    out = oracle.search([y.astype(np.float64) for y in ys], tw, kappa)
+    ref = None
+    for c in range(1, count + 1):
+        for t in (1, 2, 3):
+            with bfs.Plan(n, 4096.0, kappa=kappa, templates=temps, precision="f32", candidate=c, tile=t) as plan:
+                assert plan.kernel_info()["tile"] == t
+                with plan.filter(_dev(ys, np.float32)) as job:
+                    got = (job.fetch_tails()[0], job.fetch_sigma())
+            if t == 1:
+                ref = got
+                assert np.max(np.abs(got[1] - out["sigma"]) / out["sigma"]) <= TOL["f32"]
+                common, _ = compare_tails(got[0], out["tails"], out["sigma"], kappa, TOL["f32"],
+                                          lambda s, j: oracle.correlate_fft(ys[s].astype(np.float64), tw[j]))
+                print(f"split candidate {c}: {len(got[0])} tails, {common} common with the oracle")
+                assert common > 0
+            else:
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (c, t)
+
+
 def test_time_symmetric_bank_spectra_and_c1_search(bfs):
     # time-symmetric templates (chirp plus its reversal) synthesised on the device: spectra at
     # every plan length against the oracle, and the C1 search in FP64 against the oracle
