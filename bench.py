@@ -37,7 +37,7 @@ PEAK_HBM = 8.0e12             # MI355X HBM3E, B/s
 # only for the kernel sources and build flags they were taken on
 # (profiles/corr_loop_kernel_C2_N65536_K8192_hbm.md).
 MEASURED_TRAFFIC = {
-    "babccb152e8229dd": {"f32": 2.1928e+09, "f32-w16f": 1.0872e+09, "f32-w16b": 1.0887e+09, "f32 fused": 7.0088e+06},
+    "b182d19ef50e545a": {"f32": 2.2069e+09, "f32-w16f": 1.0879e+09, "f32-w16b": 1.0888e+09, "f32 fused": 7.0090e+06},
 }
 
 

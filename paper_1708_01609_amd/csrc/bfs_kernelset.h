@@ -7,10 +7,23 @@
 // which keeps the build parallel.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <type_traits>
 
 #include "bfs_fused.h"
+
+// A correlation launch that carries the job's timing events in its own dispatch
+// (E0 recorded as the kernel starts, E1 as it ends) when either is given, instead
+// of as separate packets between the kernels on the stream.
+#define BFS_LAUNCH_TIMED(K, GRID, BLOCK, ST, E0, E1, ...)                      \
+  do {                                                                       \
+    if ((E0) || (E1))                                                        \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, 0, ST, E0, E1, 0, __VA_ARGS__);   \
+    else                                                                     \
+      hipLaunchKernelGGL(K, GRID, BLOCK, 0, ST, __VA_ARGS__);                \
+  } while (0)
 
 namespace bfs {
 
@@ -70,6 +83,10 @@ struct CorrArgs {
   int sym;
   uint32_t rows;
   uint32_t cus;  // compute units of the device (looping sets size their grid by it; 0: one item per workgroup)
+  // timing events of the job (may be null): ev_start with the call's first launch, ev_stop
+  // with each launch, so the last one's end stands
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t ev_stop = nullptr;
 };
 
 struct KernelSet {
@@ -146,9 +163,9 @@ struct Impl {
   template <bool DENSE, int NZ>
   static void launch_fused(uint32_t blocks, const cx<T>* y, const uint32_t* seg_ids, const uint64_t* proj_off,
                            uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0, uint32_t row0, hipStream_t st,
-                           const CorrArgs& a) {
+                           const CorrArgs& a, hipEvent_t e0, hipEvent_t e1) {
     if constexpr (FUSED) {
-      hipLaunchKernelGGL((corr_fused_kernel<T, F, DENSE, G, NZ>), dim3(blocks), dim3(F::NT), 0, st, y, seg_ids,
+      BFS_LAUNCH_TIMED((corr_fused_kernel<T, F, DENSE, G, NZ>), dim3(blocks), dim3(F::NT), st, e0, e1, y, seg_ids,
                          static_cast<const cx<T>*>(a.tw_u), static_cast<const cx<T>*>(a.tw1),
                          static_cast<const cx<T>*>(a.tw2), a.f0 + j0, a.fdot + j0, a.len + j0, a.norm + j0, a.fs,
                          a.taper, a.sym, kn, rn, tile, a.kappa, a.sigma, static_cast<tail_rec_t<T>*>(a.tails),
@@ -159,7 +176,7 @@ struct Impl {
   template <bool DENSE, int MODE>
   static void launch_corr(uint32_t blocks, const TW* bank, const cx<T>* y, const uint32_t* seg_ids,
                           const uint64_t* proj_off, uint32_t kn, uint32_t rn, uint32_t tile, uint32_t j0,
-                          uint32_t row0, hipStream_t st, const CorrArgs& a) {
+                          uint32_t row0, hipStream_t st, const CorrArgs& a, hipEvent_t e0, hipEvent_t e1) {
     const auto* tu = static_cast<const cx<T>*>(a.tw_u);
     const auto* t1 = static_cast<const cx<T>*>(a.tw1);
     const auto* t2 = static_cast<const cx<T>*>(a.tw2);
@@ -168,23 +185,23 @@ struct Impl {
     constexpr bool PAIR = MODE == MODE_PAIR;
     if constexpr (MODE == MODE_FUSED) {
       if (a.rows <= uint32_t(FUSED_NZ))
-        launch_fused<DENSE, FUSED_NZ>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
+        launch_fused<DENSE, FUSED_NZ>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a, e0, e1);
       else
-        launch_fused<DENSE, F::R1>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a);
+        launch_fused<DENSE, F::R1>(blocks, y, seg_ids, proj_off, kn, rn, tile, j0, row0, st, a, e0, e1);
     } else if constexpr (LOOP && !PAIR && !SPLIT) {
-      hipLaunchKernelGGL((corr_loop_kernel<T, TW, F, DENSE, G>), dim3(loop_grid(blocks, a.cus)), dim3(F::NT), 0, st,
-                         bank, y, seg_ids, tu, t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap,
+      BFS_LAUNCH_TIMED((corr_loop_kernel<T, TW, F, DENSE, G>), dim3(loop_grid(blocks, a.cus)), dim3(F::NT), st, e0,
+                       e1, bank, y, seg_ids, tu, t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap,
                          a.proj, proj_off, a.kappa_hi, rho, j0, a.K, row0, blocks);
     } else if constexpr (PAIR && !SPLIT)
-      hipLaunchKernelGGL((pair_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
+      BFS_LAUNCH_TIMED((pair_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), st, e0, e1, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
     else if constexpr (SPLIT)
-      hipLaunchKernelGGL((corr2_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
+      BFS_LAUNCH_TIMED((corr2_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), st, e0, e1, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
     else
-      hipLaunchKernelGGL((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), 0, st, bank, y, seg_ids, tu,
+      BFS_LAUNCH_TIMED((corr_kernel<T, TW, F, DENSE, G>), dim3(blocks), dim3(F::NT), st, e0, e1, bank, y, seg_ids, tu,
                          t1, t2, kn, rn, tile, a.kappa, a.sigma, tails, a.counter, a.cap, a.proj, proj_off,
                          a.kappa_hi, rho, j0, a.K, row0);
   }
@@ -219,6 +236,7 @@ struct Impl {
     if (8ull * ((kc + 7) / 8) > max_blocks) kc = (max_blocks / 8) * 8;
     const auto* bank = static_cast<const TW*>(a.bank);
     const auto* y = static_cast<const cx<T>*>(a.y);
+    hipEvent_t e0 = a.ev_start;  // with the first launch only
     for (uint64_t j0 = 0; j0 < a.K; j0 += kc) {
       const uint32_t kn = uint32_t(std::min<uint64_t>(kc, a.K - j0));
       const uint64_t per_row = 8ull * ((kn + 7) / 8);
@@ -233,9 +251,10 @@ struct Impl {
         const uint32_t* ids = a.seg_ids ? a.seg_ids + r0 : nullptr;
         const uint64_t* po = a.proj_off ? a.proj_off + r0 : nullptr;
         if (dense)
-          launch_corr<true, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+          launch_corr<true, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a, e0, a.ev_stop);
         else
-          launch_corr<false, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a);
+          launch_corr<false, MODE>(blocks, bk, yr, ids, po, kn, rn, tile, uint32_t(j0), r0, st, a, e0, a.ev_stop);
+        e0 = nullptr;
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
       }

@@ -954,8 +954,9 @@ void set_fused_args(const bfs_plan* p, const SizePlan& sp, CorrArgs& c) {
 }
 
 // Queue the second part on cs: one fused correlation kernel per group, then
-// (projection plans) the compaction of the projection keys.  ev[1] / ev[2]
-// bracket the correlation kernels when with_events is set.
+// (projection plans) the compaction of the projection keys.  With with_events,
+// ev[1] / ev[2] are recorded as the first correlation kernel starts and the last
+// one ends (by the launches themselves).
 bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense, void* rho, double* sigma,
                         hipStream_t cs, bool with_events, uint32_t first = 0, uint32_t count = 0) {
   if (!count) count = p->K;
@@ -966,9 +967,13 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
   const auto* dlag0 = dpoff + S;
   const auto* dids = reinterpret_cast<const uint32_t*>(dlag0 + S + 1);
   char* ybase = static_cast<char*>(b->y);
-  if (with_events) HIP_TRY(hipEventRecord(b->ev[1], cs));
-  for (const Group& g : L.groups) {
+  // ev[1] / ev[2] ride on the first and the last correlation launch
+  if (with_events && L.groups.empty()) HIP_TRY(hipEventRecord(b->ev[1], cs));
+  for (size_t gi = 0; gi < L.groups.size(); ++gi) {
+    const Group& g = L.groups[gi];
     CorrArgs c{};
+    c.ev_start = with_events && gi == 0 ? b->ev[1] : nullptr;
+    c.ev_stop = with_events && gi + 1 == L.groups.size() ? b->ev[2] : nullptr;
     c.bank = p->fused ? nullptr
                       : static_cast<const char*>(g.sp->bank) + uint64_t(first) * g.sp->M * g.sp->ks->spec_size;
     c.y = ybase + (p->fused ? g.yf_off : g.y_off);
@@ -1001,7 +1006,7 @@ bfs_status enqueue_corr(bfs_plan* p, JobBuffers* b, const Layout& L, bool dense,
       HIP_TRY(p->pairs ? g.sp->ks->corr_pair(dense, g.count, cs, c) : g.sp->ks->corr(dense, g.count, cs, c));
     }
   }
-  if (with_events) HIP_TRY(hipEventRecord(b->ev[2], cs));
+  if (with_events && L.groups.empty()) HIP_TRY(hipEventRecord(b->ev[2], cs));
   if (project) {
     const uint64_t n = L.need.proj;
     const uint32_t blocks = uint32_t(std::min<uint64_t>((n + 255) / 256, 4096));
