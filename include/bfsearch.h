@@ -351,9 +351,10 @@ bfs_status bfsearch_fetch_coincidences(bfs_job* job, bfs_coinc* out_host, uint64
 bfs_status bfsearch_fetch_sigma(bfs_job* job, double* out_host);
 
 /* Device time of the job's kernels in milliseconds, measured with HIP events
- * on the streams the kernels run on: *corr_ms brackets the fused correlation kernels (the
- * whole replayed graph for BFS_PLAN_GRAPH plans), *total_ms the whole job.
- * Waits for the job. */
+ * on the streams the kernels run on: *corr_ms from the start of the first fused
+ * correlation kernel to the end of the last (events recorded by those launches
+ * themselves; the whole replayed graph for BFS_PLAN_GRAPH plans), *total_ms the
+ * whole job.  Waits for the job. */
 bfs_status bfsearch_job_timing(bfs_job* job, float* corr_ms, float* total_ms);
 
 /* Non-blocking completion check: *done = 1 once every kernel of the job has
